@@ -1,0 +1,289 @@
+"""Python face of the FP64 oracle.
+
+TEST INFRASTRUCTURE: only ``tests/``, the package smoke check and the CPU-baseline leg
+of the benchmark import this module.  The GPU renderer never does.
+
+The renderer and its gradient live in ``oit_oracle.c`` (plain C, double precision,
+single-threaded) and are reached here through ctypes.  The remaining, much smaller
+pieces of the training step are written here in numpy float64, each as its textbook
+definition:
+
+* L1 loss and its gradient (the photometric term of the 3DGS loss, which the paper
+  keeps: Sec. 5.1 "Implementation Details");
+* activeness score and active-set selection (Sec. 4.1, Eq. "activeness" and the
+  text after it: a splat is active if at least one attribute group's gradient norm
+  exceeds its threshold; top-k selection breaks ties by the lower index);
+* Adam on a subset of rows (Sec. 4.1, Alg. "Active Set Method": only the active
+  splats are updated; the optimiser is Adam, Sec. 5.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboit_oracle.so")
+SRC_PATH = os.path.join(HERE, "oit_oracle.c")
+
+GROUPS = (("mean", 3), ("log_scale", 3), ("quat", 4), ("opacity_logit", 1), ("sh", 48), ("vsh", 16))
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+               SRC_PATH, "-lm", "-o", LIB_PATH]
+        subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("height", ctypes.c_int),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("near_z", ctypes.c_double)]
+
+
+class _Splats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_long)] + [(g, ctypes.c_void_p) for g, _ in GROUPS]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [(g, ctypes.c_void_p) for g, _ in GROUPS]
+
+
+class _Win(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int), ("y0", ctypes.c_int), ("x1", ctypes.c_int), ("y1", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.orc_project.argtypes = [P, ctypes.c_double, P, P]
+        L.orc_render.argtypes = [P, ctypes.c_double, P, P, P, ctypes.c_int, P, P, P, P, P,
+                                 ctypes.c_double, P, P]
+        L.orc_render_pixels.argtypes = [P, ctypes.c_double, P, P, ctypes.c_long, P, P, P, P, P]
+        L.orc_backward.argtypes = [P, ctypes.c_double, P, P, P, P, P, P, P]
+        L.orc_backward_pixels.argtypes = [P, ctypes.c_double, P, P, ctypes.c_long, P, P, P, P, P]
+        L.orc_sh_basis.argtypes = [P, P, P]
+        L.orc_quat_to_rot.argtypes = [P, P]
+        for f in (L.orc_project, L.orc_render, L.orc_render_pixels, L.orc_backward,
+                  L.orc_backward_pixels):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class _Pack:
+    """Holds float64 copies of the parameters and the ctypes structs pointing at them."""
+
+    def __init__(self, params: dict):
+        self.arrays = {g: np.ascontiguousarray(params[g], dtype=np.float64) for g, _ in GROUPS}
+        self.n = self.arrays["mean"].shape[1]
+        self.s = _Splats(self.n, *[self.arrays[g].ctypes.data for g, _ in GROUPS])
+
+
+def _cam(c):
+    return _Cam(int(c.width), int(c.height), float(c.fx), float(c.fy), float(c.cx), float(c.cy),
+                (ctypes.c_double * 9)(*np.asarray(c.R, np.float64).reshape(-1).tolist()),
+                (ctypes.c_double * 3)(*np.asarray(c.t, np.float64).reshape(-1).tolist()),
+                float(getattr(c, "near", 0.2)))
+
+
+def _win(window, cam):
+    if window is None:
+        return _Win(0, 0, cam.width, cam.height)
+    x0, y0, x1, y1 = window
+    return _Win(int(x0), int(y0), int(x1), int(y1))
+
+
+def sh_basis(direction):
+    d = np.ascontiguousarray(direction, np.float64)
+    Y = np.zeros(16)
+    dY = np.zeros(48)
+    lib().orc_sh_basis(_ptr(d), _ptr(Y), _ptr(dY))
+    return Y, dY.reshape(16, 3)
+
+
+def quat_to_rot(q):
+    q = np.ascontiguousarray(q, np.float64)
+    R = np.zeros(9)
+    lib().orc_quat_to_rot(_ptr(q), _ptr(R))
+    return R.reshape(3, 3)
+
+
+PROJECT_FIELDS = ("valid", "mx", "my", "conic_xx", "conic_xy", "conic_yy", "opacity",
+                  "c_r", "c_g", "c_b", "v", "d", "w", "tau", "cov_xx", "cov_xy", "cov_yy",
+                  "x0", "x1", "y0", "y1")
+
+
+def project(params, sigma, cam):
+    """Per-splat screen-space quantities, [n][21] (fields in PROJECT_FIELDS)."""
+    pk = _Pack(params)
+    out = np.zeros((pk.n, len(PROJECT_FIELDS)))
+    c = _cam(cam)
+    lib().orc_project(ctypes.byref(pk.s), float(sigma), ctypes.byref(c), _ptr(out))
+    return out
+
+
+def render(params, sigma, bg, cam, include=None, brute=False, window=None, near_margin=0.0):
+    """Dense FP64 render of one view.
+
+    Returns dict with image [3][H][W], state [5][H][W] (T, Q, F), pre [9][H][W]
+    (P0 rgb, P1 rgb, Q0, Q1, logT of the rendered subset), near [H][W] bool mask of
+    pixels touched by a pair within ``near_margin`` (relative) of alpha = 1/255,
+    pairs (contributing pair count) and signature (hash of all discrete decisions).
+    """
+    pk = _Pack(params)
+    H, W = cam.height, cam.width
+    image = np.zeros((3, H, W))
+    state = np.zeros((5, H, W))
+    pre = np.zeros((9, H, W))
+    near = np.zeros((H, W), np.uint8)
+    pairs = ctypes.c_longlong(0)
+    sig = ctypes.c_ulonglong(0)
+    inc = None if include is None else np.ascontiguousarray(include, np.uint8)
+    c = _cam(cam)
+    w = _win(window, cam)
+    bgd = np.ascontiguousarray(bg, np.float64)
+    rc = lib().orc_render(ctypes.byref(pk.s), float(sigma), _ptr(bgd), ctypes.byref(c), _ptr(inc),
+                          int(bool(brute)), ctypes.byref(w), _ptr(image), _ptr(state), _ptr(pre),
+                          _ptr(near), float(near_margin), ctypes.byref(pairs), ctypes.byref(sig))
+    assert rc == 0
+    return dict(image=image, state=state, pre=pre, near=near.astype(bool), pairs=pairs.value,
+                signature=sig.value)
+
+
+def render_pixels(params, sigma, bg, cam, xs, ys):
+    """Pixel-major FP64 render of a list of pixels: (C [npix][3], state [npix][5], pairs)."""
+    pk = _Pack(params)
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    C = np.zeros((len(xs), 3))
+    st = np.zeros((len(xs), 5))
+    pairs = ctypes.c_longlong(0)
+    c = _cam(cam)
+    bgd = np.ascontiguousarray(bg, np.float64)
+    rc = lib().orc_render_pixels(ctypes.byref(pk.s), float(sigma), _ptr(bgd), ctypes.byref(c),
+                                 len(xs), _ptr(xs), _ptr(ys), _ptr(C), _ptr(st), ctypes.byref(pairs))
+    assert rc == 0
+    return C, st, pairs.value
+
+
+def _zero_grads(n):
+    return {g: np.zeros((c, n)) for g, c in GROUPS}
+
+
+def backward(params, sigma, bg, cam, dLdC, window=None, screen=False):
+    """Gradient of sum(dLdC * C) over the window (dLdC [3][H][W]).
+
+    Returns (grads dict [C][N] float64, d/dsigma, screen [n][10] or None).
+    """
+    pk = _Pack(params)
+    grads = _zero_grads(pk.n)
+    gr = _Grads(*[grads[g].ctypes.data for g, _ in GROUPS])
+    gs = ctypes.c_double(0.0)
+    scr = np.zeros((pk.n, 10)) if screen else None
+    c = _cam(cam)
+    w = _win(window, cam)
+    g = np.ascontiguousarray(dLdC, np.float64)
+    bgd = np.ascontiguousarray(bg, np.float64)
+    rc = lib().orc_backward(ctypes.byref(pk.s), float(sigma), _ptr(bgd), ctypes.byref(c),
+                            ctypes.byref(w), _ptr(g), ctypes.byref(gr), ctypes.byref(gs), _ptr(scr))
+    assert rc == 0
+    return grads, gs.value, scr
+
+
+def backward_pixels(params, sigma, bg, cam, xs, ys, dLdC):
+    """Gradient of sum_k dLdC[k] . C(pixel k) for a pixel list (dLdC [npix][3])."""
+    pk = _Pack(params)
+    grads = _zero_grads(pk.n)
+    gr = _Grads(*[grads[g].ctypes.data for g, _ in GROUPS])
+    gs = ctypes.c_double(0.0)
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    g = np.ascontiguousarray(dLdC, np.float64)
+    c = _cam(cam)
+    bgd = np.ascontiguousarray(bg, np.float64)
+    rc = lib().orc_backward_pixels(ctypes.byref(pk.s), float(sigma), _ptr(bgd), ctypes.byref(c),
+                                   len(xs), _ptr(xs), _ptr(ys), _ptr(g), ctypes.byref(gr),
+                                   ctypes.byref(gs))
+    assert rc == 0
+    return grads, gs.value
+
+
+# ----------------------------------------------------------------------------------
+# Loss, activeness, selection and Adam (numpy float64)
+# ----------------------------------------------------------------------------------
+
+def l1_loss(image, target):
+    """L = mean |C - I| over the 3HW values; dL/dC = sign(C - I) / (3HW), sign(0) = 0."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    n = d.size
+    return float(np.abs(d).sum() / n), np.sign(d) / n
+
+
+def activeness_score(grads: dict, rows, eps=None):
+    """s_i = max over groups g of ||grad_g(i)||_2 / eps_g (Sec. 4.1, Eq. "activeness",
+    read with "at least one group" as the text after it says).  ``grads`` holds the
+    [C][len(rows)] gradients of the listed rows."""
+    eps = eps or {g: 1.0 for g, _ in GROUPS}
+    s = np.zeros(len(rows))
+    for g, _ in GROUPS:
+        nrm = np.sqrt((np.asarray(grads[g], np.float64) ** 2).sum(axis=0))
+        s = np.maximum(s, nrm / eps[g])
+    return s
+
+
+def select_topk(score, k):
+    """The k largest scores; ties to the lower index; returned sorted ascending."""
+    score = np.asarray(score)
+    order = sorted(range(len(score)), key=lambda i: (-float(score[i]), i))
+    return np.array(sorted(order[:k]), dtype=np.int64)
+
+
+def select_threshold(score, thresh=1.0):
+    return np.nonzero(np.asarray(score) > thresh)[0].astype(np.int64)
+
+
+def label_delta(old_label, new_idx, n):
+    """New label byte per splat and the label changes, ascending by index.
+
+    sign -1: the splat entered the active set (its share leaves the pre-render);
+    sign +1: the splat left the active set (its share joins the pre-render).
+    """
+    new_label = np.zeros(n, np.uint8)
+    new_label[np.asarray(new_idx, np.int64)] = 1
+    old = np.asarray(old_label, np.uint8)
+    changed = np.nonzero(old != new_label)[0]
+    sign = np.where(new_label[changed] == 1, -1, 1).astype(np.int8)
+    return new_label, changed.astype(np.int64), sign
+
+
+def adam_rows(param, grad_rows, m, v, rows, lr, beta1, beta2, eps, step):
+    """Adam on the listed rows of a [C][N] parameter (in place, float64).
+
+    grad_rows is [C][len(rows)] in the order of ``rows``.  Bias correction uses the
+    global step count; rows not listed keep their values and moments untouched.
+    """
+    rows = np.asarray(rows, np.int64)
+    g = np.asarray(grad_rows, np.float64)
+    m[:, rows] = beta1 * m[:, rows] + (1.0 - beta1) * g
+    v[:, rows] = beta2 * v[:, rows] + (1.0 - beta2) * g * g
+    mhat = m[:, rows] / (1.0 - beta1 ** step)
+    vhat = v[:, rows] / (1.0 - beta2 ** step)
+    param[:, rows] = param[:, rows] - lr * mhat / (np.sqrt(vhat) + eps)
