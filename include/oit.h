@@ -1,0 +1,263 @@
+/*
+ * liboit — sort-free order-independent-transparency (OIT) Gaussian-splat renderer
+ * for AMD Instinct MI355X (gfx950): forward, backward, active-set selection and a
+ * sparse Adam step, as hand-written HIP kernels behind a plain C ABI.
+ *
+ * The method is SparseOIT (arXiv 2605.13855):
+ *   - weighted OIT composite  C = T c0 + (1 - T) P / Q,  T = prod_i (1 - alpha_i),
+ *     P = sum_i c_i alpha_i w_i,  Q = sum_i alpha_i w_i      (Sec. 3.2, Eq. "oit_rendering");
+ *   - per-splat weight w = max(0, 1 - d / sigma) v(r), sigma a learnable scene scalar,
+ *     v a single-channel degree-3 SH                            (Sec. 1, Eq. "sf_weight";
+ *                                                               Sec. 5.1 "Implementation Details");
+ *   - rasteriser that bins splats into screen tiles and sorts entries by tile only,
+ *     no depth sort; one pass blends the active splats and normalises ("BAN") and
+ *     updates the pre-rendered buffer of the inactive set ("BAU")     (App. A, Alg. "rasterize");
+ *   - closed-form partials dC/dc, dC/dalpha, dC/dw              (App. B, Eq. "oit_rendering_detail");
+ *   - active set: a splat is active if some attribute group's gradient is large
+ *     (Sec. 4.1, Eq. "activeness"); only active splats are rendered against the
+ *     pre-rendered image of the others and updated by Adam   (Sec. 4.1, Alg. "Active Set Method").
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked (host).
+ *   - Splat parameters are float32, component-major ("SoA"): a group with C components
+ *     is a [C][n] array (row c at offset c * n).  The colour SH is [16][3][n]
+ *     (coefficient, channel, splat); quaternions are (w, x, y, z), any length.
+ *   - Per-view images are planar float32.  A batch of V views is packed view after
+ *     view: view k starts at plane offset P * pix_base(k), pix_base(k) = sum_{j<k} H_j W_j,
+ *     and holds P planes of H_k x W_k (P = 3 for images, 5 for pixstate, 9 for pre).
+ *   - Pixel (x, y) has its centre at (x + 0.5, y + 0.5); cameras are pinhole, OpenCV
+ *     axes (+x right, +y down, +z forward), x_cam = R x_world + t.
+ *   - The caller owns all memory (inputs, outputs and the workspace).  The library
+ *     never allocates, frees or synchronises inside these calls; all work is enqueued
+ *     on `stream`, so every call can be captured into a HIP graph.
+ *   - Errors: invalid arguments are detected on the host and returned synchronously
+ *     (OIT_ERR_INVALID, nothing is enqueued); a HIP launch error returns OIT_ERR_HIP.
+ *     Data-dependent capacity overflows (more tile entries, active rows or label
+ *     changes than the buffers hold) cannot be seen on the host: the kernels bound
+ *     every write, set a bit in the device status word of the workspace and the
+ *     results of that call are incomplete; read it with oit_read_status.
+ *     oit_last_error() returns a message for the last failing call on this thread.
+ *   - NaN inputs propagate; there are no device-side checks of values.
+ */
+#ifndef OIT_H
+#define OIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *oit_stream; /* a hipStream_t */
+
+typedef enum {
+    OIT_OK = 0,
+    OIT_ERR_INVALID = -1,
+    OIT_ERR_HIP = -2,
+    OIT_ERR_CAPACITY = -3,
+    OIT_ERR_WORKSPACE = -4
+} oit_status;
+
+/* bits of the device status word */
+#define OIT_STATUS_PAIR_OVERFLOW 1   /* tile entries exceeded tuning.pair_capacity */
+#define OIT_STATUS_ACTIVE_OVERFLOW 2 /* selection produced more rows than active capacity */
+#define OIT_STATUS_DELTA_OVERFLOW 4  /* more label changes than delta capacity */
+
+#define OIT_MAX_VIEWS 64
+
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy; /* pixels */
+    float R[9];           /* world -> camera rotation, row-major */
+    float t[3];
+    float near_z;         /* splats with camera-space depth <= near_z are culled (0.2) */
+} oit_camera;             /* (host) */
+
+typedef struct {
+    int64_t n;
+    const float *mean;          /* [3][n] */
+    const float *log_scale;     /* [3][n]   scale = exp(log_scale) */
+    const float *quat;          /* [4][n]   (w, x, y, z) */
+    const float *opacity_logit; /* [n]      opacity = sigmoid(logit) */
+    const float *sh;            /* [16][3][n] colour SH, degree 3 */
+    const float *vsh;           /* [16][n]  view-weight SH, degree 3 */
+} oit_splats;
+
+/* Gradients of the active rows, compact: row r of a group is the r-th entry of
+ * active_idx (or splat r in dense mode); group with C components is [C][stride]. */
+typedef struct {
+    float *mean, *log_scale, *quat, *opacity_logit, *sh, *vsh;
+    int64_t stride;
+} oit_grads;
+
+typedef struct {
+    int32_t tile;           /* tile edge in pixels: 8, 16 or 32 */
+    int32_t batch;          /* splat records staged in LDS per forward batch: 32..256 */
+    int64_t pair_capacity;  /* capacity of the (tile, splat) entry list */
+} oit_tuning;               /* (host) */
+
+/* Sizes that fix the workspace of render_fwd / render_bwd (host). */
+typedef struct {
+    int64_t n;              /* splats in the scene */
+    int64_t active_capacity;/* max active rows (n for dense rendering) */
+    int64_t delta_capacity; /* max label changes per call (0 without pre-rendering) */
+} oit_capacity;
+
+/*
+ * Bytes of workspace that oit_render_fwd / oit_render_bwd need for these views, sizes
+ * and tuning; 0 on invalid arguments.  The forward pass leaves its projected splat
+ * records, tile lists and per-pixel data in the workspace and the backward pass of
+ * the same call sequence reads them, so both must get the same workspace, cameras,
+ * capacities and tuning, with the splat parameters unchanged in between.
+ */
+size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int32_t n_views,
+                           const oit_tuning *tuning);
+
+/*
+ * Forward pass over V = n_views cameras (App. A, Alg. "rasterize"): project the rows
+ * in the active list and in the label-change list, bin them into tiles (no depth
+ * order), then per pixel blend the active splats, update the pre-rendered buffer with
+ * the label changes and normalise:
+ *   P = P_A + P0 - P1 / sigma,  Q = Q_A + Q0 - Q1 / sigma,  T = T_A exp(logT),
+ *   F = P / Q (0 if Q <= 0),    C = T bg + (1 - T) F.
+ *
+ * splats      scene parameters (all n rows; only listed rows are read)
+ * sigma       [1] device float, the weight's depth scale (> 0)
+ * bg          (host) [3] background colour c0
+ * cams        (host) [n_views] cameras, 1 <= n_views <= OIT_MAX_VIEWS
+ * active_idx  [active_capacity] int32 splat ids of the active set, ascending;
+ *             NULL renders all n splats (dense mode; n_active, delta_* must be NULL)
+ * n_active    [1] device int32 count of active_idx entries used (<= active_capacity)
+ * delta_idx   [delta_capacity] int32 splat ids whose label changed, delta_sign[k] = -1
+ *             for a splat that joined the active set (its share leaves pre) and +1 for
+ *             one that left it (its share joins pre); n_delta [1] device int32.
+ *             All three NULL when no label changed.
+ * pre         [V][9][H][W] per-pixel accumulators of the inactive set: P0 (rgb),
+ *             P1 (rgb), Q0, Q1, logT with P0 = sum c alpha v, P1 = sum c alpha v d,
+ *             Q0 = sum alpha v, Q1 = sum alpha v d over inactive splats with d < sigma,
+ *             logT = sum log(1 - alpha) over all inactive splats; updated in place by
+ *             the label changes.  NULL in dense mode.
+ * image       [V][3][H][W] output C
+ * pixstate    [V][5][H][W] output T, Q, F (rgb): what the backward pass needs
+ * ws          workspace of oit_workspace_bytes(...) bytes, 256-byte aligned
+ */
+oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const float *bg,
+                          const oit_camera *cams, int32_t n_views, const oit_capacity *cap,
+                          const int32_t *active_idx, const int32_t *n_active,
+                          const int32_t *delta_idx, const int8_t *delta_sign, const int32_t *n_delta,
+                          float *pre, float *image, float *pixstate,
+                          void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream);
+
+/*
+ * L1 photometric loss over the batch (the L1 term of the 3DGS loss that the paper
+ * keeps, Sec. 5.1): loss = sum_views mean_{3 H W} |C - target| and
+ * grad_image = sign(C - target) / (3 H W) per view (sign(0) = 0).
+ * image, target, grad_image [V][3][H][W]; loss [1] device double (overwritten).
+ */
+oit_status oit_l1_loss(const float *image, const float *target, const oit_camera *cams,
+                       int32_t n_views, float *grad_image, double *loss,
+                       void *ws, size_t ws_bytes, oit_stream stream);
+
+/*
+ * Backward pass (App. B, Eq. "oit_rendering_detail", then the chain rule through the
+ * projection): given dL/dC for every view, write the gradient of every parameter of
+ * the active rows and of sigma.  Each splat's gradient is independent of the others
+ * (App. B), so the kernel runs one splat per lane over its tile's pixels.
+ * The inactive splats' share of d/dsigma comes from pre (P1, Q1).
+ *
+ * grad_image  [V][3][H][W] dL/dC
+ * pixstate    the forward pass's output
+ * grads       output, compact rows in active_idx order (overwritten; rows beyond
+ *             n_active untouched)
+ * grad_sigma  [1] device double (overwritten)
+ * score       [n] float, or NULL: written at the active splats' ids with
+ *             max over groups g of ||dL/dtheta_g||_2 / eps[g] (Sec. 4.1, Eq. "activeness")
+ * eps         (host) [6] per-group thresholds in the group order mean, log_scale, quat,
+ *             opacity, sh, vsh; NULL means all 1
+ * Other arguments as in oit_render_fwd, with the same values.
+ */
+oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const float *bg,
+                          const oit_camera *cams, int32_t n_views, const oit_capacity *cap,
+                          const int32_t *active_idx, const int32_t *n_active,
+                          const int32_t *delta_idx, const int8_t *delta_sign, const int32_t *n_delta,
+                          const float *pre, const float *grad_image, const float *pixstate,
+                          const oit_grads *grads, double *grad_sigma,
+                          float *score, const float *eps,
+                          void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream);
+
+#define OIT_SELECT_TOPK 0
+#define OIT_SELECT_THRESHOLD 1
+
+/* Workspace bytes of oit_update_active_set for n splats. */
+size_t oit_select_workspace_bytes(int64_t n);
+
+/*
+ * Active-set update (Sec. 4.1): pick the new active set from per-splat scores and
+ * emit the label changes relative to the current labels.
+ *   mode OIT_SELECT_TOPK:      the k largest scores; ties go to the lower splat id.
+ *   mode OIT_SELECT_THRESHOLD: every splat with score > thresh (the paper's rule:
+ *                              some group's gradient norm above its threshold).
+ * score      [n] float, >= 0
+ * label      [n] uint8 in/out: 1 = active.  On return holds the new labels.
+ * active_idx [active_capacity] out, ascending; n_active [1] device int32 out
+ * delta_idx  [delta_capacity] out, ascending; delta_sign [delta_capacity] int8 out
+ *            (-1 joined, +1 left); n_delta [1] device int32 out
+ * Counts above the capacities set the status word's overflow bits; the lists then
+ * hold the first `capacity` entries.
+ */
+oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, int64_t k, float thresh,
+                                 uint8_t *label, int32_t *active_idx, int64_t active_capacity,
+                                 int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign,
+                                 int64_t delta_capacity, int32_t *n_delta,
+                                 void *ws, size_t ws_bytes, oit_stream stream);
+
+/*
+ * Adam on the active rows only (Sec. 4.1, Alg. "Active Set Method": the update
+ * touches only the active splats; the optimiser is Adam, Sec. 5.1).
+ * For every active row i (splat id active_idx[r], compact gradient row r) and
+ * component:  m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *             theta -= lr_g * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * Rows outside the active set, their moments included, are not touched.
+ * params/m/v  [6] pointers to the [C][n] groups (mean, log_scale, quat, opacity_logit,
+ *             sh, vsh); grads as written by oit_render_bwd
+ * active_idx  NULL for dense (all n rows); n_active device count or NULL (= n)
+ * lr          (host) [6] per-group learning rates
+ * step        [1] device int32: incremented by this call, then used as t.
+ */
+oit_status oit_sparse_adam_step(float *const *params, const oit_grads *grads, float *const *m,
+                                float *const *v, const int32_t *active_idx, const int32_t *n_active,
+                                int64_t n, const float *lr, float beta1, float beta2, float eps,
+                                int32_t *step, oit_stream stream);
+
+/*
+ * Adam step on sigma from its FP64 gradient (same rule, one scalar): sigma, m, v [1]
+ * device float; step [1] device int32, incremented by this call then used as t.
+ */
+oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m, float *v,
+                               float lr, float beta1, float beta2, float eps, int32_t *step,
+                               oit_stream stream);
+
+/* Wait for `stream` and copy the workspace's device status word to *out (host). */
+oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream);
+
+/*
+ * Wait for `stream` and report the number of (tile, splat) entries the last
+ * oit_render_fwd on this workspace needed (also when it overflowed
+ * tuning.pair_capacity), so that a caller can size pair_capacity and run again.
+ * Arguments as given to that oit_render_fwd; *out (host).
+ */
+oit_status oit_read_pair_total(const void *ws, size_t ws_bytes, const oit_capacity *cap,
+                               const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,
+                               int64_t *out, oit_stream stream);
+
+/* Clear the status word (enqueued on `stream`). */
+oit_status oit_clear_status(void *ws, size_t ws_bytes, oit_stream stream);
+
+/* Message of the last failing call on the calling thread ("" if none). */
+const char *oit_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OIT_H */

@@ -1,0 +1,503 @@
+// Forward pass: projection, tile binning without depth order, and the per-pixel
+// blend-and-normalise / blend-and-update pass (App. A, Alg. "rasterize").
+#include "oit_internal.h"
+
+namespace oit {
+
+// ---------------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------------
+struct CamChunk {
+    CamDev c[8];
+};
+
+__global__ void k_upload_cams(CamChunk chunk, int n, CamDev *dst)
+{
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = chunk.c[i];
+}
+
+void upload_cams(const CamDev *host, int n_views, CamDev *dst, hipStream_t s)
+{
+    for (int base = 0; base < n_views; base += 8) {
+        CamChunk ch;
+        const int k = n_views - base < 8 ? n_views - base : 8;
+        for (int i = 0; i < k; ++i) ch.c[i] = host[base + i];
+        hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, s, ch, k, dst + base);
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n, T v)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+static void fill_any(T *p, size_t n, T v, hipStream_t s)
+{
+    if (n == 0) return;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) { fill_any(p, n, v, s); }
+void fill_f32(float *p, size_t n, float v, hipStream_t s) { fill_any(p, n, v, s); }
+void fill_f64(double *p, size_t n, double v, hipStream_t s) { fill_any(p, n, v, s); }
+
+// ---------------------------------------------------------------------------------
+// row lookup shared by the per-record kernels
+// ---------------------------------------------------------------------------------
+// Returns the splat id of record t, or -1 if the record is unused in this call.
+// sign: 0 for an active record, -1 / +1 for a label change.
+__device__ __forceinline__ int64_t record_row(const RowList &rl, int64_t t, int &sign)
+{
+    if (t < rl.Acap) {
+        const int64_t na = rl.n_active ? (int64_t)*rl.n_active : rl.n_active_host;
+        if (t >= na) return -1;
+        sign = 0;
+        return rl.active_idx ? (int64_t)rl.active_idx[t] : t;
+    }
+    const int64_t k = t - rl.Acap;
+    const int64_t nd = rl.n_delta ? (int64_t)*rl.n_delta : 0;
+    if (k >= nd) return -1;
+    sign = rl.delta_sign[k] < 0 ? -1 : 1;
+    return (int64_t)rl.delta_idx[k];
+}
+
+// Tile test of the record in the rasteriser's own units: the record's exponent is
+// e = lo - m' with m' = A dx^2 + 2 B dx dy + C dy^2, A = -qa, B = -qb / 2, C = -qc;
+// a pair contributes iff m' <= lo + log2(255).  The bound is widened slightly so that
+// a tile is never dropped for a pair the per-pixel float test would keep.
+__device__ __forceinline__ float tile_tau(float lo) { return (lo - kLog2AlphaMin) * 1.0001f + 1e-4f; }
+
+__device__ __forceinline__ bool tile_hit(const Rec &r, float tau, const CamDev &cam, int S, int tx, int ty)
+{
+    const float px0 = (float)(tx * S) + 0.5f;
+    const float px1 = (float)min(tx * S + S, cam.W) - 0.5f;
+    const float py0 = (float)(ty * S) + 0.5f;
+    const float py1 = (float)min(ty * S + S, cam.H) - 0.5f;
+    return ellipse_hits_rect(-r.a.z, -0.5f * r.a.w, -r.b.x, tau, px0 - r.a.x, px1 - r.a.x, py0 - r.a.y,
+                             py1 - r.a.y);
+}
+
+// ---------------------------------------------------------------------------------
+// preprocess: one thread per listed splat, all views; writes the records, the tile
+// rectangles and counts the tile entries.
+// ---------------------------------------------------------------------------------
+struct PreArgs {
+    SplatPtrs sp;
+    const float *sigma;
+    RowList rl;
+    Buffers b;
+};
+
+__global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.rl.Rcap) return;
+    int sign = 0;
+    const int64_t id = record_row(a.rl, t, sign);
+    if (id < 0) return;
+    const int64_t n = a.sp.n;
+    const float sigma = *a.sigma;
+
+    float mu[3], s[3], q[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mu[k] = a.sp.mean[k * n + id];
+        s[k] = expf(a.sp.log_scale[k * n + id]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[k * n + id];
+    const float qi = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    float Rq[9], S6[6];
+    quat_rot(q[0] * qi, q[1] * qi, q[2] * qi, q[3] * qi, Rq);
+    cov3d(Rq, s, S6);
+    const float lg = a.sp.logit[id];
+    const float lo = -log2f(1.f + expf(-lg));   // log2(sigmoid(logit))
+    float shc[48], vsc[16];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) shc[k] = a.sp.sh[k * n + id];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) vsc[k] = a.sp.vsh[k * n + id];
+
+    const int S = a.b.tile;
+    for (int v = 0; v < a.b.n_views; ++v) {
+        const CamDev &cam = a.b.cams[v];
+        const size_t ri = (size_t)v * a.rl.Rcap + t;
+        Rec r;
+        short4 rect = make_short4(0, 0, 0, 0);
+        Geo g;
+        if (geometry(cam, mu, S6, g)) {
+            float dir[3] = {mu[0] - cam.cc[0], mu[1] - cam.cc[1], mu[2] - cam.cc[2]};
+            const float di = rsqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+            dir[0] *= di;
+            dir[1] *= di;
+            dir[2] *= di;
+            float Y[16];
+            sh_eval(dir[0], dir[1], dir[2], Y);
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = kColorOffset;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc += Y[k] * shc[3 * k + ch];
+                col[ch] = fmaxf(acc, 0.f);
+            }
+            float vr = kColorOffset;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) vr += Y[k] * vsc[k];
+            const float vv = fmaxf(vr, 0.f);
+            const float d = g.tc[2];
+            const bool w_on = d < sigma;
+            const float w = w_on ? (1.f - d / sigma) * vv : 0.f;
+            const float h = -0.5f * kLog2e;
+            r.a = make_float4(g.mx, g.my, h * g.con_a, 2.f * h * g.con_b);
+            r.b = make_float4(h * g.con_c, lo, col[0], col[1]);
+            if (sign == 0)
+                r.c = make_float4(col[2], w, 0.f, 1.f);
+            else
+                r.c = make_float4(col[2], w_on ? vv : 0.f, d, (float)sign);
+
+            const float tau = tile_tau(lo);
+            if (tau > 0.f) {
+                // footprint box of the (slightly widened) level set, in pixels, +1 px
+                const float tau_px = tau * 2.f * kLn2;   // back to units of the unscaled form
+                const float hx = sqrtf(tau_px * g.cov_a), hy = sqrtf(tau_px * g.cov_c);
+                const float xl = fminf(fmaxf(g.mx - hx - 0.5f, -1e7f), 1e7f);
+                const float xh = fminf(fmaxf(g.mx + hx - 0.5f, -1e7f), 1e7f);
+                const float yl = fminf(fmaxf(g.my - hy - 0.5f, -1e7f), 1e7f);
+                const float yh = fminf(fmaxf(g.my + hy - 0.5f, -1e7f), 1e7f);
+                int x0 = (int)floorf(xl) - 1, x1 = (int)ceilf(xh) + 1;
+                int y0 = (int)floorf(yl) - 1, y1 = (int)ceilf(yh) + 1;
+                x0 = max(x0, 0);
+                y0 = max(y0, 0);
+                x1 = min(x1, cam.W - 1);
+                y1 = min(y1, cam.H - 1);
+                if (x0 <= x1 && y0 <= y1) {
+                    rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
+                    uint32_t *cnt = sign == 0 ? a.b.cnt_a : a.b.cnt_d;
+                    for (int ty = rect.z; ty < rect.w; ++ty)
+                        for (int tx = rect.x; tx < rect.y; ++tx)
+                            if (tile_hit(r, tau, cam, S, tx, ty))
+                                atomicAdd(&cnt[cam.tile_base + ty * cam.tiles_x + tx], 1u);
+                }
+            }
+        } else {
+            r.a = make_float4(0.f, 0.f, 0.f, 0.f);
+            r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
+            r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        a.b.rec[ri] = r;
+        a.b.rect[ri] = rect;
+    }
+}
+
+void launch_preprocess_count(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
+                             hipStream_t s)
+{
+    PreArgs a{sp, sigma, rl, b};
+    const unsigned blocks = (unsigned)((rl.Rcap + 255) / 256);
+    if (blocks) hipLaunchKernelGGL(k_preprocess_count, dim3(blocks), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------------
+// exclusive scans of per-tile entry counts and backward chunk counts (one block)
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
+{
+    __shared__ unsigned long long s_e[kScanThreads];
+    __shared__ unsigned long long s_c[kScanThreads];
+    const int T = b.T;
+    const int tid = threadIdx.x;
+    const int seg = (T + kScanThreads - 1) / kScanThreads;
+    const int t0 = min(tid * seg, T), t1 = min(t0 + seg, T);
+    unsigned long long se = 0, sc = 0;
+    for (int t = t0; t < t1; ++t) {
+        const uint32_t na = b.cnt_a[t];
+        se += na + b.cnt_d[t];
+        sc += (na + kBwdLanes - 1) / kBwdLanes;
+    }
+    s_e[tid] = se;
+    s_c[tid] = sc;
+    __syncthreads();
+    // Hillis-Steele inclusive scan
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        unsigned long long ve = tid >= off ? s_e[tid - off] : 0ull;
+        unsigned long long vc = tid >= off ? s_c[tid - off] : 0ull;
+        __syncthreads();
+        s_e[tid] += ve;
+        s_c[tid] += vc;
+        __syncthreads();
+    }
+    unsigned long long pe = s_e[tid] - se, pc = s_c[tid] - sc;
+    const unsigned long long cap = (unsigned long long)b.pair_cap;
+    for (int t = t0; t < t1; ++t) {
+        b.tile_off[t] = (uint32_t)(pe < cap ? pe : cap);
+        b.chunk_off[t] = (uint32_t)pc;
+        const uint32_t na = b.cnt_a[t];
+        pe += na + b.cnt_d[t];
+        pc += (na + kBwdLanes - 1) / kBwdLanes;
+    }
+    if (tid == kScanThreads - 1) {
+        const unsigned long long te = s_e[tid], tc = s_c[tid];
+        b.tile_off[T] = (uint32_t)(te < cap ? te : cap);
+        b.chunk_off[T] = (uint32_t)tc;
+        b.counters[CNT_TOTAL_CHUNKS] = (uint32_t)tc;
+        b.counters[CNT_TOTAL_ENTRIES] = (uint32_t)(te < 0xffffffffull ? te : 0xffffffffull);
+        if (te > cap) atomicOr(b.status, OIT_STATUS_PAIR_OVERFLOW);
+    }
+}
+
+void launch_scan_tiles(const Buffers &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, b);
+}
+
+// ---------------------------------------------------------------------------------
+// emit: place each (tile, record) entry; active entries first within a tile
+// ---------------------------------------------------------------------------------
+struct EmitArgs {
+    RowList rl;
+    Buffers b;
+};
+
+__global__ __launch_bounds__(256) void k_emit(EmitArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.rl.Rcap) return;
+    int sign = 0;
+    if (record_row(a.rl, t, sign) < 0) return;
+    const int S = a.b.tile;
+    const uint64_t cap = (uint64_t)a.b.pair_cap;
+    for (int v = 0; v < a.b.n_views; ++v) {
+        const CamDev &cam = a.b.cams[v];
+        const size_t ri = (size_t)v * a.rl.Rcap + t;
+        const short4 rect = a.b.rect[ri];
+        if (rect.x >= rect.y || rect.z >= rect.w) continue;
+        const Rec r = a.b.rec[ri];
+        const float tau = tile_tau(r.b.y);
+        for (int ty = rect.z; ty < rect.w; ++ty)
+            for (int tx = rect.x; tx < rect.y; ++tx) {
+                if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
+                const int tile = cam.tile_base + ty * cam.tiles_x + tx;
+                uint64_t pos;
+                if (sign == 0) {
+                    const uint32_t slot = atomicAdd(&a.b.fill_a[tile], 1u);
+                    if (slot >= a.b.cnt_a[tile]) continue;
+                    pos = (uint64_t)a.b.tile_off[tile] + slot;
+                } else {
+                    const uint32_t slot = atomicAdd(&a.b.fill_d[tile], 1u);
+                    if (slot >= a.b.cnt_d[tile]) continue;
+                    pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
+                }
+                if (pos < cap) a.b.entries[pos] = (uint32_t)t;
+            }
+    }
+}
+
+void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s)
+{
+    EmitArgs a{rl, b};
+    const unsigned blocks = (unsigned)((rl.Rcap + 255) / 256);
+    if (blocks) hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------------
+// raster forward: one workgroup per tile (all views of the batch in one launch).
+// Records of the tile's entries are staged through LDS in batches; every thread
+// blends them into its pixels in list order (no depth order).
+// ---------------------------------------------------------------------------------
+struct FwdArgs {
+    Buffers b;
+    const float *sigma;
+    float bg0, bg1, bg2;
+    float *pre, *image, *pixstate;
+};
+
+// A record that contributes nothing (its exponent is always below the threshold);
+// stands in for any tile-list entry outside its class's record range.
+__device__ const Rec kNoRec = {{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+
+template <int S, int BATCH>
+__global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArgs a)
+{
+    constexpr int NT = S * S < 256 ? S * S : 256;
+    constexpr int PPT = S * S / NT;
+    __shared__ float4 s_rec[BATCH * 3];
+
+    const int tile = blockIdx.x;
+    const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
+    const CamDev &cam = a.b.cams[v];
+    const int lt = tile - cam.tile_base;
+    const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+
+    float px[PPT], py[PPT];
+    float P[PPT][3], Q[PPT], T[PPT];
+    float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int li = threadIdx.x + p * NT;
+        px[p] = (float)(tx * S + li % S) + 0.5f;
+        py[p] = (float)(ty * S + li / S) + 0.5f;
+        P[p][0] = P[p][1] = P[p][2] = 0.f;
+        Q[p] = 0.f;
+        T[p] = 1.f;
+        dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
+        dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
+        dQ0[p] = dQ1[p] = dL[p] = 0.f;
+    }
+
+    const uint64_t cap = (uint64_t)a.b.pair_cap;
+    const uint64_t off = a.b.tile_off[tile];
+    uint64_t na = a.b.cnt_a[tile], nd = a.b.cnt_d[tile];
+    if (off + na > cap) na = off < cap ? cap - off : 0;
+    if (off + na + nd > cap) nd = off + na < cap ? cap - off - na : 0;
+    const Rec *recv = a.b.rec + (size_t)v * a.b.Rcap;
+
+    // active entries: BAN accumulators
+    for (uint64_t base = 0; base < na; base += BATCH) {
+        const int cnt = (int)(na - base < (uint64_t)BATCH ? na - base : (uint64_t)BATCH);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t ri = a.b.entries[off + base + j];
+            const Rec r = ri < a.b.Acap ? recv[ri] : kNoRec;
+            s_rec[3 * j] = r.a;
+            s_rec[3 * j + 1] = r.b;
+            s_rec[3 * j + 2] = r.c;
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
+                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
+                if (e >= kLog2AlphaMin) {
+                    const float al = fminf(exp2f(e), kAlphaMax);
+                    const float aw = al * rc.y;
+                    P[p][0] = fmaf(rb.z, aw, P[p][0]);
+                    P[p][1] = fmaf(rb.w, aw, P[p][1]);
+                    P[p][2] = fmaf(rc.x, aw, P[p][2]);
+                    Q[p] += aw;
+                    T[p] *= 1.f - al;
+                }
+            }
+        }
+    }
+    // label changes: BAU accumulators (sign-weighted, sigma-free)
+    for (uint64_t base = 0; base < nd; base += BATCH) {
+        const int cnt = (int)(nd - base < (uint64_t)BATCH ? nd - base : (uint64_t)BATCH);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t ri = a.b.entries[off + na + base + j];
+            const Rec r = (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec;
+            s_rec[3 * j] = r.a;
+            s_rec[3 * j + 1] = r.b;
+            s_rec[3 * j + 2] = r.c;
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
+                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
+                if (e >= kLog2AlphaMin) {
+                    const float al = fminf(exp2f(e), kAlphaMax);
+                    const float sav = rc.w * al * rc.y;       // sign * alpha * v
+                    const float savd = sav * rc.z;            // ... * d
+                    dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
+                    dP0[p][1] = fmaf(rb.w, sav, dP0[p][1]);
+                    dP0[p][2] = fmaf(rc.x, sav, dP0[p][2]);
+                    dP1[p][0] = fmaf(rb.z, savd, dP1[p][0]);
+                    dP1[p][1] = fmaf(rb.w, savd, dP1[p][1]);
+                    dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
+                    dQ0[p] += sav;
+                    dQ1[p] += savd;
+                    dL[p] = fmaf(rc.w, logf(1.f - al), dL[p]);
+                }
+            }
+        }
+    }
+
+    const float sigma = *a.sigma;
+    const float isig = 1.f / sigma;
+    const size_t HW = (size_t)cam.W * cam.H;
+    const size_t pb = (size_t)cam.pix_base;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int x = (int)px[p], y = (int)py[p];
+        if (x >= cam.W || y >= cam.H) continue;
+        const size_t pix = (size_t)y * cam.W + x;
+        float Pt[3] = {P[p][0], P[p][1], P[p][2]};
+        float Qt = Q[p], Tt = T[p];
+        if (a.pre) {
+            float *pr = a.pre + 9 * pb;
+            float pv[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW + pix];
+            if (nd) {
+                pv[0] += dP0[p][0];
+                pv[1] += dP0[p][1];
+                pv[2] += dP0[p][2];
+                pv[3] += dP1[p][0];
+                pv[4] += dP1[p][1];
+                pv[5] += dP1[p][2];
+                pv[6] += dQ0[p];
+                pv[7] += dQ1[p];
+                pv[8] += dL[p];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pr[k * HW + pix] = pv[k];
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) Pt[ch] += pv[ch] - pv[3 + ch] * isig;
+            Qt += pv[6] - pv[7] * isig;
+            Tt *= expf(pv[8]);
+        }
+        const float iq = Qt > 0.f ? 1.f / Qt : 0.f;
+        const float F0 = Pt[0] * iq, F1 = Pt[1] * iq, F2 = Pt[2] * iq;
+        float *im = a.image + 3 * pb;
+        im[pix] = Tt * a.bg0 + (1.f - Tt) * F0;
+        im[HW + pix] = Tt * a.bg1 + (1.f - Tt) * F1;
+        im[2 * HW + pix] = Tt * a.bg2 + (1.f - Tt) * F2;
+        float *ps = a.pixstate + 5 * pb;
+        ps[pix] = Tt;
+        ps[HW + pix] = Qt;
+        ps[2 * HW + pix] = F0;
+        ps[3 * HW + pix] = F1;
+        ps[4 * HW + pix] = F2;
+    }
+}
+
+template <int S>
+static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s)
+{
+    constexpr int NT = S * S < 256 ? S * S : 256;
+    const dim3 grid((unsigned)a.b.T), block(NT);
+    switch (batch) {
+    case 32: hipLaunchKernelGGL((k_raster_fwd<S, 32>), grid, block, 0, s, a); return true;
+    case 64: hipLaunchKernelGGL((k_raster_fwd<S, 64>), grid, block, 0, s, a); return true;
+    case 128: hipLaunchKernelGGL((k_raster_fwd<S, 128>), grid, block, 0, s, a); return true;
+    case 256: hipLaunchKernelGGL((k_raster_fwd<S, 256>), grid, block, 0, s, a); return true;
+    default: return false;
+    }
+}
+
+bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
+                       float *pixstate, int batch, hipStream_t s)
+{
+    FwdArgs a{b, sigma, bg[0], bg[1], bg[2], pre, image, pixstate};
+    if (b.T == 0) return true;
+    switch (b.tile) {
+    case 8: return raster_fwd_s<8>(a, batch, s);
+    case 16: return raster_fwd_s<16>(a, batch, s);
+    case 32: return raster_fwd_s<32>(a, batch, s);
+    default: return false;
+    }
+}
+
+}  // namespace oit

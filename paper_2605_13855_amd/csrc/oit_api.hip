@@ -1,0 +1,456 @@
+// C ABI of liboit: argument validation on the host, the workspace plan and the
+// launch sequence of each entry point.  No allocation, no synchronisation (except
+// oit_read_status, which exists to synchronise).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "oit_internal.h"
+
+using namespace oit;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+oit_status fail(oit_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+oit_status ok()
+{
+    g_err[0] = 0;
+    return OIT_OK;
+}
+
+oit_status check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(OIT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+struct Plan {
+    size_t status, cams, counters, tiles, tile_off, chunk_off, entries, rec, rect, sgrad, pixconst, total;
+    int T;
+    int64_t total_px, Acap, Rcap;
+    CamDev cams_host[kMaxViews];
+};
+
+oit_status check_cams(const oit_camera *cams, int32_t n_views)
+{
+    if (!cams) return fail(OIT_ERR_INVALID, "cams is NULL");
+    if (n_views < 1 || n_views > OIT_MAX_VIEWS)
+        return fail(OIT_ERR_INVALID, "n_views = %d outside [1, %d]", n_views, OIT_MAX_VIEWS);
+    for (int v = 0; v < n_views; ++v) {
+        const oit_camera &c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768)
+            return fail(OIT_ERR_INVALID, "camera %d: bad size %dx%d", v, c.width, c.height);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+            return fail(OIT_ERR_INVALID, "camera %d: bad intrinsics", v);
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(c.R[k])) return fail(OIT_ERR_INVALID, "camera %d: non-finite R", v);
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(c.t[k])) return fail(OIT_ERR_INVALID, "camera %d: non-finite t", v);
+        if (!(c.near_z > 0.f)) return fail(OIT_ERR_INVALID, "camera %d: near_z must be > 0", v);
+    }
+    return OIT_OK;
+}
+
+oit_status check_tuning(const oit_tuning *tu)
+{
+    if (!tu) return fail(OIT_ERR_INVALID, "tuning is NULL");
+    if (tu->tile != 8 && tu->tile != 16 && tu->tile != 32)
+        return fail(OIT_ERR_INVALID, "tuning.tile = %d not in {8, 16, 32}", tu->tile);
+    if (tu->batch != 32 && tu->batch != 64 && tu->batch != 128 && tu->batch != 256)
+        return fail(OIT_ERR_INVALID, "tuning.batch = %d not in {32, 64, 128, 256}", tu->batch);
+    if (tu->pair_capacity <= 0 || tu->pair_capacity >= 0xffffffffLL)
+        return fail(OIT_ERR_INVALID, "tuning.pair_capacity = %lld outside [1, 2^32 - 1)",
+                    (long long)tu->pair_capacity);
+    return OIT_OK;
+}
+
+oit_status check_cap(const oit_capacity *cap)
+{
+    if (!cap) return fail(OIT_ERR_INVALID, "capacity is NULL");
+    if (cap->n <= 0 || cap->n > 0x7fffffffLL) return fail(OIT_ERR_INVALID, "n = %lld outside [1, 2^31)", (long long)cap->n);
+    if (cap->active_capacity <= 0 || cap->active_capacity > cap->n)
+        return fail(OIT_ERR_INVALID, "active_capacity = %lld outside [1, n]", (long long)cap->active_capacity);
+    if (cap->delta_capacity < 0 || cap->delta_capacity > cap->n)
+        return fail(OIT_ERR_INVALID, "delta_capacity = %lld outside [0, n]", (long long)cap->delta_capacity);
+    return OIT_OK;
+}
+
+oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_views, const oit_tuning *tu,
+                     Plan &p)
+{
+    oit_status st;
+    if ((st = check_cap(cap)) != OIT_OK) return st;
+    if ((st = check_cams(cams, n_views)) != OIT_OK) return st;
+    if ((st = check_tuning(tu)) != OIT_OK) return st;
+    const int S = tu->tile;
+    int64_t tiles = 0, px = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const oit_camera &c = cams[v];
+        CamDev &d = p.cams_host[v];
+        memset(&d, 0, sizeof(d));
+        for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+        for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+        d.fx = c.fx;
+        d.fy = c.fy;
+        d.cx = c.cx;
+        d.cy = c.cy;
+        d.near_z = c.near_z;
+        d.lim_x = kGuardBand * (0.5f * (float)c.width / c.fx);
+        d.lim_y = kGuardBand * (0.5f * (float)c.height / c.fy);
+        for (int r = 0; r < 3; ++r)
+            d.cc[r] = (float)(-((double)c.R[r] * c.t[0] + (double)c.R[3 + r] * c.t[1] + (double)c.R[6 + r] * c.t[2]));
+        d.W = c.width;
+        d.H = c.height;
+        d.tiles_x = (c.width + S - 1) / S;
+        d.tiles_y = (c.height + S - 1) / S;
+        d.tile_base = (int)tiles;
+        d.pix_base = (int)px;
+        tiles += (int64_t)d.tiles_x * d.tiles_y;
+        px += (int64_t)c.width * c.height;
+        if (tiles > 0x7fffffffLL || px > 0x7fffffffLL / 9)
+            return fail(OIT_ERR_INVALID, "batch too large: %lld tiles, %lld pixels", (long long)tiles, (long long)px);
+    }
+    p.T = (int)tiles;
+    p.total_px = px;
+    p.Acap = cap->active_capacity;
+    p.Rcap = cap->active_capacity + cap->delta_capacity;
+    size_t o = 0;
+    p.status = o; o = align256(o + 4);
+    p.cams = o; o = align256(o + sizeof(CamDev) * kMaxViews);
+    p.counters = o; o = align256(o + 4 * CNT_SLOTS);
+    p.tiles = o; o = align256(o + 4 * 4 * (size_t)p.T);
+    p.tile_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
+    p.chunk_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
+    p.entries = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
+    p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
+    p.rect = o; o = align256(o + sizeof(short4) * (size_t)n_views * p.Rcap);
+    p.sgrad = o; o = align256(o + 4 * 10 * (size_t)n_views * p.Acap);
+    p.pixconst = o; o = align256(o + 32 * (size_t)p.total_px);
+    p.total = o;
+    return OIT_OK;
+}
+
+Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
+{
+    char *w = (char *)ws;
+    Buffers b;
+    b.status = (int32_t *)(w + p.status);
+    b.cams = (CamDev *)(w + p.cams);
+    b.counters = (uint32_t *)(w + p.counters);
+    b.cnt_a = (uint32_t *)(w + p.tiles);
+    b.cnt_d = b.cnt_a + p.T;
+    b.fill_a = b.cnt_d + p.T;
+    b.fill_d = b.fill_a + p.T;
+    b.tile_off = (uint32_t *)(w + p.tile_off);
+    b.chunk_off = (uint32_t *)(w + p.chunk_off);
+    b.entries = (uint32_t *)(w + p.entries);
+    b.rec = (Rec *)(w + p.rec);
+    b.rect = (short4 *)(w + p.rect);
+    b.sgrad = (float *)(w + p.sgrad);
+    b.pixconst = (float4 *)(w + p.pixconst);
+    b.n_views = n_views;
+    b.T = p.T;
+    b.tile = tu->tile;
+    b.total_px = p.total_px;
+    b.pair_cap = tu->pair_capacity;
+    b.Acap = p.Acap;
+    b.Rcap = p.Rcap;
+    return b;
+}
+
+oit_status check_splats(const oit_splats *s, const oit_capacity *cap)
+{
+    if (!s) return fail(OIT_ERR_INVALID, "splats is NULL");
+    if (s->n != cap->n) return fail(OIT_ERR_INVALID, "splats.n = %lld differs from capacity.n = %lld",
+                                    (long long)s->n, (long long)cap->n);
+    const void *ptrs[6] = {s->mean, s->log_scale, s->quat, s->opacity_logit, s->sh, s->vsh};
+    const char *names[6] = {"mean", "log_scale", "quat", "opacity_logit", "sh", "vsh"};
+    for (int k = 0; k < 6; ++k) {
+        if (!ptrs[k]) return fail(OIT_ERR_INVALID, "splats.%s is NULL", names[k]);
+        if (!aligned(ptrs[k], 4)) return fail(OIT_ERR_INVALID, "splats.%s is not 4-byte aligned", names[k]);
+    }
+    return OIT_OK;
+}
+
+oit_status check_rows(const oit_capacity *cap, const int32_t *active_idx, const int32_t *n_active,
+                      const int32_t *delta_idx, const int8_t *delta_sign, const int32_t *n_delta, const void *pre)
+{
+    if (!active_idx) {
+        if (n_active || delta_idx || delta_sign || n_delta)
+            return fail(OIT_ERR_INVALID, "dense mode (active_idx NULL) takes no n_active or label changes");
+        if (cap->active_capacity != cap->n)
+            return fail(OIT_ERR_INVALID, "dense mode needs active_capacity == n");
+        return OIT_OK;
+    }
+    if (!n_active) return fail(OIT_ERR_INVALID, "active_idx given without n_active");
+    const bool any = delta_idx || delta_sign || n_delta;
+    const bool all = delta_idx && delta_sign && n_delta;
+    if (any && !all) return fail(OIT_ERR_INVALID, "delta_idx, delta_sign and n_delta go together");
+    if (all && !pre) return fail(OIT_ERR_INVALID, "label changes need the pre-rendered buffer");
+    if (all && cap->delta_capacity <= 0) return fail(OIT_ERR_INVALID, "label changes need delta_capacity > 0");
+    return OIT_OK;
+}
+
+RowList rows(const oit_capacity *cap, const int32_t *active_idx, const int32_t *n_active, const int32_t *delta_idx,
+             const int8_t *delta_sign, const int32_t *n_delta, const Plan &p)
+{
+    RowList r;
+    r.active_idx = active_idx;
+    r.n_active = n_active;
+    r.n_active_host = active_idx ? 0 : cap->n;
+    r.delta_idx = delta_idx;
+    r.delta_sign = delta_sign;
+    r.n_delta = n_delta;
+    r.Acap = p.Acap;
+    r.Rcap = p.Rcap;
+    return r;
+}
+
+SplatPtrs splat_ptrs(const oit_splats *s)
+{
+    return SplatPtrs{s->mean, s->log_scale, s->quat, s->opacity_logit, s->sh, s->vsh, s->n};
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int32_t n_views,
+                           const oit_tuning *tuning)
+{
+    Plan p;
+    if (make_plan(cap, cams, n_views, tuning, p) != OIT_OK) return 0;
+    return p.total;
+}
+
+oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const float *bg, const oit_camera *cams,
+                          int32_t n_views, const oit_capacity *cap, const int32_t *active_idx,
+                          const int32_t *n_active, const int32_t *delta_idx, const int8_t *delta_sign,
+                          const int32_t *n_delta, float *pre, float *image, float *pixstate, void *ws,
+                          size_t ws_bytes, const oit_tuning *tuning, oit_stream stream)
+{
+    Plan p;
+    oit_status st;
+    if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
+    if ((st = check_splats(splats, cap)) != OIT_OK) return st;
+    if ((st = check_rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, pre)) != OIT_OK) return st;
+    if (!sigma || !bg || !image || !pixstate) return fail(OIT_ERR_INVALID, "sigma, bg, image and pixstate are required");
+    if (!aligned(image, 4) || !aligned(pixstate, 4) || (pre && !aligned(pre, 4)))
+        return fail(OIT_ERR_INVALID, "image buffers must be 4-byte aligned");
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < p.total)
+        return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+    hipStream_t s = (hipStream_t)stream;
+    const Buffers b = buffers(p, ws, n_views, tuning);
+    const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
+    upload_cams(p.cams_host, n_views, b.cams, s);
+    fill_u32(b.cnt_a, 4 * (size_t)p.T, 0u, s);
+    launch_preprocess_count(splat_ptrs(splats), sigma, rl, b, s);
+    launch_scan_tiles(b, s);
+    launch_emit(rl, b, s);
+    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s))
+        return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
+    return check_launch("oit_render_fwd");
+}
+
+oit_status oit_l1_loss(const float *image, const float *target, const oit_camera *cams, int32_t n_views,
+                       float *grad_image, double *loss, void *ws, size_t ws_bytes, oit_stream stream)
+{
+    oit_status st;
+    if ((st = check_cams(cams, n_views)) != OIT_OK) return st;
+    if (!image || !target || !grad_image || !loss) return fail(OIT_ERR_INVALID, "oit_l1_loss: NULL buffer");
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    // the loss only needs the camera table at the head of the workspace
+    const size_t need = align256(4) + sizeof(CamDev) * kMaxViews;
+    if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    oit_capacity cap{1, 1, 0};
+    oit_tuning tu{16, 64, 1};
+    Plan p;
+    if ((st = make_plan(&cap, cams, n_views, &tu, p)) != OIT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Buffers b = buffers(p, ws, n_views, &tu);
+    upload_cams(p.cams_host, n_views, b.cams, s);
+    launch_l1_loss(b, image, target, grad_image, loss, s);
+    return check_launch("oit_l1_loss");
+}
+
+oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const float *bg, const oit_camera *cams,
+                          int32_t n_views, const oit_capacity *cap, const int32_t *active_idx,
+                          const int32_t *n_active, const int32_t *delta_idx, const int8_t *delta_sign,
+                          const int32_t *n_delta, const float *pre, const float *grad_image,
+                          const float *pixstate, const oit_grads *grads, double *grad_sigma, float *score,
+                          const float *eps, void *ws, size_t ws_bytes, const oit_tuning *tuning,
+                          oit_stream stream)
+{
+    Plan p;
+    oit_status st;
+    if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
+    if ((st = check_splats(splats, cap)) != OIT_OK) return st;
+    if ((st = check_rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, pre)) != OIT_OK) return st;
+    if (!sigma || !bg || !grad_image || !pixstate || !grads || !grad_sigma)
+        return fail(OIT_ERR_INVALID, "sigma, bg, grad_image, pixstate, grads and grad_sigma are required");
+    const void *gp[6] = {grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->vsh};
+    for (int k = 0; k < 6; ++k)
+        if (!gp[k] || !aligned(gp[k], 4)) return fail(OIT_ERR_INVALID, "gradient buffer %d NULL or misaligned", k);
+    if (grads->stride < cap->active_capacity)
+        return fail(OIT_ERR_INVALID, "grads.stride = %lld < active_capacity", (long long)grads->stride);
+    if (!aligned(grad_sigma, 8)) return fail(OIT_ERR_INVALID, "grad_sigma must be 8-byte aligned");
+    float e6[6] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+    if (eps)
+        for (int k = 0; k < 6; ++k) {
+            if (!(eps[k] > 0.f)) return fail(OIT_ERR_INVALID, "eps[%d] must be > 0", k);
+            e6[k] = eps[k];
+        }
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < p.total)
+        return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+    hipStream_t s = (hipStream_t)stream;
+    const Buffers b = buffers(p, ws, n_views, tuning);
+    const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
+    const GradPtrs g{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->vsh,
+                     grads->stride};
+    upload_cams(p.cams_host, n_views, b.cams, s);
+    fill_f32(b.sgrad, 10 * (size_t)n_views * p.Acap, 0.f, s);
+    fill_u32(b.counters + CNT_BWD_WORK, 1, 0u, s);
+    fill_f64(grad_sigma, 1, 0.0, s);
+    launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
+    if (!launch_raster_bwd(b, rl, s)) return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
+    launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
+    return check_launch("oit_render_bwd");
+}
+
+size_t oit_select_workspace_bytes(int64_t n)
+{
+    if (n <= 0) return 0;
+    const int64_t nblk = (n + 1023) / 1024;
+    size_t o = 0;
+    o = align256(o + 4);              // status
+    o = align256(o + 4 * 8);          // state
+    o = align256(o + 4 * 2048);       // hist
+    o = align256(o + 4 * 3 * (size_t)(nblk + 1));
+    o = align256(o + (size_t)n);      // flags
+    return o;
+}
+
+oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, int64_t k, float thresh,
+                                 uint8_t *label, int32_t *active_idx, int64_t active_capacity, int32_t *n_active,
+                                 int32_t *delta_idx, int8_t *delta_sign, int64_t delta_capacity, int32_t *n_delta,
+                                 void *ws, size_t ws_bytes, oit_stream stream)
+{
+    if (n <= 0 || n > 0x7fffffffLL) return fail(OIT_ERR_INVALID, "n = %lld outside [1, 2^31)", (long long)n);
+    if (mode != OIT_SELECT_TOPK && mode != OIT_SELECT_THRESHOLD)
+        return fail(OIT_ERR_INVALID, "mode = %d unknown", mode);
+    if (!score || !label || !active_idx || !n_active || !delta_idx || !delta_sign || !n_delta)
+        return fail(OIT_ERR_INVALID, "oit_update_active_set: NULL buffer");
+    if (active_capacity <= 0 || delta_capacity <= 0)
+        return fail(OIT_ERR_INVALID, "capacities must be positive");
+    if (mode == OIT_SELECT_THRESHOLD && !std::isfinite(thresh))
+        return fail(OIT_ERR_INVALID, "threshold must be finite");
+    const size_t need = oit_select_workspace_bytes(n);
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const int64_t nblk = (n + 1023) / 1024;
+    char *w = (char *)ws;
+    size_t o = 0;
+    SelectBuffers sb;
+    sb.status = (int32_t *)(w + o); o = align256(o + 4);
+    sb.state = (uint32_t *)(w + o); o = align256(o + 4 * 8);
+    sb.hist = (uint32_t *)(w + o); o = align256(o + 4 * 2048);
+    sb.blk_a = (uint32_t *)(w + o);
+    sb.blk_b = sb.blk_a + (nblk + 1);
+    sb.blk_c = sb.blk_b + (nblk + 1);
+    o = align256(o + 4 * 3 * (size_t)(nblk + 1));
+    sb.flags = (uint8_t *)(w + o);
+    sb.nblk = nblk;
+    launch_select(score, n, mode, k, thresh, label, active_idx, active_capacity, n_active, delta_idx, delta_sign,
+                  delta_capacity, n_delta, sb, (hipStream_t)stream);
+    return check_launch("oit_update_active_set");
+}
+
+oit_status oit_sparse_adam_step(float *const *params, const oit_grads *grads, float *const *m, float *const *v,
+                                const int32_t *active_idx, const int32_t *n_active, int64_t n, const float *lr,
+                                float beta1, float beta2, float eps, int32_t *step, oit_stream stream)
+{
+    if (!params || !grads || !m || !v || !lr || !step) return fail(OIT_ERR_INVALID, "oit_sparse_adam_step: NULL argument");
+    if (n <= 0 || n > 0x7fffffffLL) return fail(OIT_ERR_INVALID, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!active_idx && n_active) return fail(OIT_ERR_INVALID, "n_active without active_idx");
+    if (active_idx && !n_active) return fail(OIT_ERR_INVALID, "active_idx without n_active");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(OIT_ERR_INVALID, "bad Adam hyper-parameters");
+    AdamPtrs a;
+    const float *gg[6] = {grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->vsh};
+    for (int k = 0; k < 6; ++k) {
+        if (!params[k] || !m[k] || !v[k] || !gg[k]) return fail(OIT_ERR_INVALID, "group %d: NULL pointer", k);
+        a.p[k] = params[k];
+        a.g[k] = gg[k];
+        a.m[k] = m[k];
+        a.v[k] = v[k];
+        a.lr[k] = lr[k];
+    }
+    const int64_t rows_cap = active_idx ? grads->stride : n;
+    if (grads->stride <= 0 || (!active_idx && grads->stride < n))
+        return fail(OIT_ERR_INVALID, "grads.stride = %lld too small", (long long)grads->stride);
+    launch_sparse_adam(a, grads->stride, active_idx, n_active, n, rows_cap, beta1, beta2, eps, step,
+                       (hipStream_t)stream);
+    return check_launch("oit_sparse_adam_step");
+}
+
+oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m, float *v, float lr, float beta1,
+                               float beta2, float eps, int32_t *step, oit_stream stream)
+{
+    if (!sigma || !grad_sigma || !m || !v || !step) return fail(OIT_ERR_INVALID, "oit_sigma_adam_step: NULL argument");
+    launch_sigma_adam(sigma, grad_sigma, m, v, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    return check_launch("oit_sigma_adam_step");
+}
+
+oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream)
+{
+    if (!ws || !out || ws_bytes < 4) return fail(OIT_ERR_INVALID, "oit_read_status: bad arguments");
+    hipError_t e = hipMemcpyAsync(out, ws, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_read_status: %s", hipGetErrorString(e));
+    return ok();
+}
+
+oit_status oit_read_pair_total(const void *ws, size_t ws_bytes, const oit_capacity *cap, const oit_camera *cams,
+                               int32_t n_views, const oit_tuning *tuning, int64_t *out, oit_stream stream)
+{
+    Plan p;
+    oit_status st;
+    if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
+    if (!ws || !out || ws_bytes < p.total) return fail(OIT_ERR_INVALID, "oit_read_pair_total: bad arguments");
+    uint32_t v = 0;
+    const char *src = (const char *)ws + p.counters + 4 * CNT_TOTAL_ENTRIES;
+    hipError_t e = hipMemcpyAsync(&v, src, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_read_pair_total: %s", hipGetErrorString(e));
+    *out = (int64_t)v;
+    return ok();
+}
+
+oit_status oit_clear_status(void *ws, size_t ws_bytes, oit_stream stream)
+{
+    if (!ws || ws_bytes < 4) return fail(OIT_ERR_INVALID, "oit_clear_status: bad arguments");
+    fill_u32((uint32_t *)ws, 1, 0u, (hipStream_t)stream);
+    return check_launch("oit_clear_status");
+}
+
+const char *oit_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal interface between the C ABI (oit_api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "oit.h"
+#include "oit_device.h"
+
+namespace oit {
+
+constexpr int kMaxViews = 64;
+constexpr int kBwdLanes = 64;   // splats per backward work item (one wave)
+constexpr int kScanThreads = 1024;
+
+// counters[] slots in the workspace
+enum { CNT_BWD_WORK = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SLOTS = 16 };
+
+struct SplatPtrs {
+    const float *mean, *log_scale, *quat, *logit, *sh, *vsh;
+    int64_t n;
+};
+
+struct GradPtrs {
+    float *mean, *log_scale, *quat, *logit, *sh, *vsh;
+    int64_t stride;
+};
+
+// Which rows a call renders: records [0, n_active) are active rows, records
+// [Acap, Acap + n_delta) are label changes.
+struct RowList {
+    const int32_t *active_idx;   // NULL: row r is splat r
+    const int32_t *n_active;     // NULL: n_active_host
+    int64_t n_active_host;
+    const int32_t *delta_idx;
+    const int8_t *delta_sign;
+    const int32_t *n_delta;      // NULL: no label changes
+    int64_t Acap, Rcap;          // Rcap = Acap + Dcap: record stride of one view
+};
+
+struct Buffers {
+    int32_t *status;
+    CamDev *cams;
+    uint32_t *counters;
+    uint32_t *cnt_a, *cnt_d, *fill_a, *fill_d;  // [T]
+    uint32_t *tile_off, *chunk_off;             // [T + 1]
+    uint32_t *entries;                          // [pair_cap]
+    Rec *rec;                                   // [V][Rcap]
+    short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
+    float *sgrad;                               // [V][Acap][10]
+    float4 *pixconst;                           // [total_px][2]
+    int n_views, T, tile;
+    int64_t total_px, pair_cap;
+    int64_t Acap, Rcap;                         // record stride: Rcap per view
+};
+
+// View of a batch tile (views are packed in order; at most kMaxViews of them).
+__device__ __forceinline__ int view_of_tile(const CamDev *cams, int n_views, int tile)
+{
+    int v = 0;
+    for (int k = 1; k < n_views; ++k)
+        if (tile >= cams[k].tile_base) v = k;
+    return v;
+}
+
+void upload_cams(const CamDev *host, int n_views, CamDev *dst, hipStream_t s);
+void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+void fill_f32(float *p, size_t n, float v, hipStream_t s);
+void fill_f64(double *p, size_t n, double v, hipStream_t s);
+
+void launch_preprocess_count(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
+                             hipStream_t s);
+void launch_scan_tiles(const Buffers &b, hipStream_t s);
+void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s);
+bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
+                       float *pixstate, int batch, hipStream_t s);
+
+void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
+                    hipStream_t s);
+void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], const float *pre,
+                     const float *grad_image, const float *pixstate, double *grad_sigma, hipStream_t s);
+bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s);
+void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
+                           const GradPtrs &g, double *grad_sigma, float *score, const float eps[6],
+                           hipStream_t s);
+
+struct SelectBuffers {
+    int32_t *status;
+    uint32_t *state;      // [8]: prefix, k_remaining, digit results
+    uint32_t *hist;       // [2048]
+    uint32_t *blk_a, *blk_b, *blk_c;  // per-block counts / offsets [nblk + 1]
+    uint8_t *flags;       // [n]
+    int64_t nblk;
+};
+void launch_select(const float *score, int64_t n, int mode, int64_t k, float thresh, uint8_t *label,
+                   int32_t *active_idx, int64_t acap, int32_t *n_active, int32_t *delta_idx,
+                   int8_t *delta_sign, int64_t dcap, int32_t *n_delta, const SelectBuffers &sb,
+                   hipStream_t s);
+
+struct AdamPtrs {
+    float *p[6];
+    const float *g[6];
+    float *m[6];
+    float *v[6];
+    float lr[6];
+};
+void launch_sparse_adam(const AdamPtrs &a, int64_t gstride, const int32_t *active_idx, const int32_t *n_active,
+                        int64_t n, int64_t rows_cap, float b1, float b2, float eps, int32_t *step,
+                        hipStream_t s);
+void launch_sigma_adam(float *sigma, const double *g, float *m, float *v, float lr, float b1, float b2,
+                       float eps, int32_t *step, hipStream_t s);
+
+}  // namespace oit

@@ -1,0 +1,220 @@
+"""ctypes binding of liboit (argument marshalling only).
+
+Each function here has the name of the C entry point without its ``oit_`` prefix,
+takes torch tensors (device memory) or ``None``, and passes their data pointers and
+the current HIP stream of torch to the library.  Every computation happens in the
+library's HIP kernels; nothing here computes on the host.  The module raises at
+import if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboit.so")
+
+OK = 0
+STATUS_PAIR_OVERFLOW = 1
+STATUS_ACTIVE_OVERFLOW = 2
+STATUS_DELTA_OVERFLOW = 4
+SELECT_TOPK = 0
+SELECT_THRESHOLD = 1
+MAX_VIEWS = 64
+GROUPS = (("mean", 3), ("log_scale", 3), ("quat", 4), ("opacity_logit", 1), ("sh", 48), ("vsh", 16))
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
+                ("near_z", ctypes.c_float)]
+
+
+class Splats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(g, ctypes.c_void_p) for g, _ in GROUPS]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [(g, ctypes.c_void_p) for g, _ in GROUPS] + [("stride", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+
+
+class Capacity(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("active_capacity", ctypes.c_int64),
+                ("delta_capacity", ctypes.c_int64)]
+
+
+class OITError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise OITError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, F, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+    L.oit_workspace_bytes.argtypes = [P, P, I32, P]
+    L.oit_workspace_bytes.restype = SZ
+    L.oit_render_fwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.oit_l1_loss.argtypes = [P, P, P, I32, P, P, P, SZ, P]
+    L.oit_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.oit_select_workspace_bytes.argtypes = [I64]
+    L.oit_select_workspace_bytes.restype = SZ
+    L.oit_update_active_set.argtypes = [P, I64, I32, I64, F, P, P, I64, P, P, P, I64, P, P, SZ, P]
+    L.oit_sparse_adam_step.argtypes = [P, P, P, P, P, P, I64, P, F, F, F, P, P]
+    L.oit_sigma_adam_step.argtypes = [P, P, P, P, F, F, F, F, P, P]
+    L.oit_read_status.argtypes = [P, SZ, P, P]
+    L.oit_clear_status.argtypes = [P, SZ, P]
+    L.oit_read_pair_total.argtypes = [P, SZ, P, P, I32, P, P, P]
+    L.oit_last_error.argtypes = []
+    L.oit_last_error.restype = ctypes.c_char_p
+    for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
+              L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
+              L.oit_read_pair_total):
+        f.restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    if not t.is_contiguous():
+        raise OITError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise OITError(f"{what} failed ({rc}): {lib.oit_last_error().decode()}")
+
+
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = [float(x) for x in list(getattr(cam.R, "reshape")(-1))]
+    t = [float(x) for x in list(getattr(cam.t, "reshape")(-1))]
+    c.R = (ctypes.c_float * 9)(*R)
+    c.t = (ctypes.c_float * 3)(*t)
+    c.near_z = float(getattr(cam, "near", 0.2))
+    return c
+
+
+def camera_array(cams):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera_struct(c)
+    return arr
+
+
+def splats_struct(params: dict) -> Splats:
+    n = params["mean"].shape[1]
+    for g, c in GROUPS:
+        t = params[g]
+        if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (c, n):
+            raise OITError(f"parameter {g} must be contiguous float32 [{c}][{n}]")
+    return Splats(n, *[params[g].data_ptr() for g, _ in GROUPS])
+
+
+def grads_struct(grads: dict, stride: int) -> Grads:
+    return Grads(*[grads[g].data_ptr() for g, _ in GROUPS], int(stride))
+
+
+def workspace_bytes(cap: Capacity, cams_arr, n_views: int, tuning: Tuning) -> int:
+    return int(lib.oit_workspace_bytes(ctypes.byref(cap), cams_arr, n_views, ctypes.byref(tuning)))
+
+
+def render_fwd(splats: Splats, sigma, bg_host, cams_arr, n_views, cap: Capacity, active_idx, n_active,
+               delta_idx, delta_sign, n_delta, pre, image, pixstate, ws, tuning: Tuning, stream=None):
+    bg = (ctypes.c_float * 3)(*[float(x) for x in bg_host])
+    rc = lib.oit_render_fwd(ctypes.byref(splats), _ptr(sigma), bg, cams_arr, n_views, ctypes.byref(cap),
+                            _ptr(active_idx), _ptr(n_active), _ptr(delta_idx), _ptr(delta_sign), _ptr(n_delta),
+                            _ptr(pre), _ptr(image), _ptr(pixstate), _ptr(ws), ws.numel(),
+                            ctypes.byref(tuning), _stream(stream))
+    _check(rc, "oit_render_fwd")
+
+
+def l1_loss(image, target, cams_arr, n_views, grad_image, loss, ws, stream=None):
+    rc = lib.oit_l1_loss(_ptr(image), _ptr(target), cams_arr, n_views, _ptr(grad_image), _ptr(loss),
+                         _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "oit_l1_loss")
+
+
+def render_bwd(splats: Splats, sigma, bg_host, cams_arr, n_views, cap: Capacity, active_idx, n_active,
+               delta_idx, delta_sign, n_delta, pre, grad_image, pixstate, grads: Grads, grad_sigma, score,
+               eps_host, ws, tuning: Tuning, stream=None):
+    bg = (ctypes.c_float * 3)(*[float(x) for x in bg_host])
+    eps = None if eps_host is None else (ctypes.c_float * 6)(*[float(x) for x in eps_host])
+    rc = lib.oit_render_bwd(ctypes.byref(splats), _ptr(sigma), bg, cams_arr, n_views, ctypes.byref(cap),
+                            _ptr(active_idx), _ptr(n_active), _ptr(delta_idx), _ptr(delta_sign), _ptr(n_delta),
+                            _ptr(pre), _ptr(grad_image), _ptr(pixstate), ctypes.byref(grads), _ptr(grad_sigma),
+                            _ptr(score), eps, _ptr(ws), ws.numel(), ctypes.byref(tuning), _stream(stream))
+    _check(rc, "oit_render_bwd")
+
+
+def select_workspace_bytes(n: int) -> int:
+    return int(lib.oit_select_workspace_bytes(int(n)))
+
+
+def update_active_set(score, n, mode, k, thresh, label, active_idx, n_active, delta_idx, delta_sign, n_delta,
+                      ws, stream=None):
+    rc = lib.oit_update_active_set(_ptr(score), int(n), int(mode), int(k), float(thresh), _ptr(label),
+                                   _ptr(active_idx), active_idx.numel(), _ptr(n_active), _ptr(delta_idx),
+                                   _ptr(delta_sign), delta_idx.numel(), _ptr(n_delta), _ptr(ws), ws.numel(),
+                                   _stream(stream))
+    _check(rc, "oit_update_active_set")
+
+
+def sparse_adam_step(params: dict, grads: Grads, m: dict, v: dict, active_idx, n_active, n, lr, beta1, beta2,
+                     eps, step, stream=None):
+    P6 = ctypes.c_void_p * 6
+    pp = P6(*[params[g].data_ptr() for g, _ in GROUPS])
+    mm = P6(*[m[g].data_ptr() for g, _ in GROUPS])
+    vv = P6(*[v[g].data_ptr() for g, _ in GROUPS])
+    lrs = (ctypes.c_float * 6)(*[float(x) for x in lr])
+    rc = lib.oit_sparse_adam_step(pp, ctypes.byref(grads), mm, vv, _ptr(active_idx), _ptr(n_active), int(n), lrs,
+                                  float(beta1), float(beta2), float(eps), _ptr(step), _stream(stream))
+    _check(rc, "oit_sparse_adam_step")
+
+
+def sigma_adam_step(sigma, grad_sigma, m, v, lr, beta1, beta2, eps, step, stream=None):
+    rc = lib.oit_sigma_adam_step(_ptr(sigma), _ptr(grad_sigma), _ptr(m), _ptr(v), float(lr), float(beta1),
+                                 float(beta2), float(eps), _ptr(step), _stream(stream))
+    _check(rc, "oit_sigma_adam_step")
+
+
+def read_status(ws, stream=None) -> int:
+    out = ctypes.c_int32(0)
+    rc = lib.oit_read_status(_ptr(ws), ws.numel(), ctypes.byref(out), _stream(stream))
+    _check(rc, "oit_read_status")
+    return int(out.value)
+
+
+def read_pair_total(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    rc = lib.oit_read_pair_total(_ptr(ws), ws.numel(), ctypes.byref(cap), cams_arr, n_views, ctypes.byref(tuning),
+                                 ctypes.byref(out), _stream(stream))
+    _check(rc, "oit_read_pair_total")
+    return int(out.value)
+
+
+def clear_status(ws, stream=None):
+    rc = lib.oit_clear_status(_ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "oit_clear_status")

@@ -1,0 +1,430 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Images within 1e-5 (normwise, per view, pixels touched by a
+float-ambiguous alpha = 1/255 pair excluded and counted), gradients within 1e-4
+(normwise per parameter group), sigma within 1e-4, integer outputs bit-exact."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2605_13855_amd import scenes
+from tests.gpu_common import (GRAD_RTOL, IMAGE_RTOL, NEAR_MARGIN, SIGMA_RTOL, compare_image, grad_floor,
+                              grad_rel, image_views, oracle_grads, to_np)
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd.render import (ActiveSetTrainer, Renderer, new_grads, params_to_device, render)
+
+DEV = "cuda"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True, windows=None, seed=0,
+               sigma_atol=0.0):
+    """Render sc densely on the GPU and in the oracle; compare image, state and grads."""
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n, tile=tile, batch=batch)
+    r.fit_pair_capacity(params, sigma, sc.background)
+    r.forward(params, sigma, sc.background)
+    torch.cuda.synchronize()
+    assert r.status() == 0
+    imgs = image_views(r, r.image, 3)
+    states = image_views(r, r.pixstate, 5)
+    worst = 0.0
+    masked = 0
+    for k, cam in enumerate(sc.cameras):
+        ref = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=near_margin)
+        err = compare_image(imgs[k], ref["image"], ref["near"])
+        masked += int(ref["near"].sum())
+        worst = max(worst, err)
+        log(f"  view {k} {cam.width}x{cam.height}: image err {err:.2e}, near-masked px {int(ref['near'].sum())}, "
+            f"pairs {ref['pairs']}")
+        assert err <= IMAGE_RTOL, (k, err)
+        # per-pixel totals T and Q on unmasked pixels
+        ok = ~ref["near"]
+        np.testing.assert_allclose(states[k][0][ok], ref["state"][0][ok], rtol=1e-4, atol=1e-6)
+    if not check_grads:
+        return r
+    rng = np.random.default_rng(seed)
+    g_views = [rng.normal(size=(3, c.height, c.width)) for c in sc.cameras]
+    if windows:
+        for k, w in enumerate(windows):
+            m = np.zeros_like(g_views[k])
+            x0, y0, x1, y1 = w
+            m[:, y0:y1, x0:x1] = 1.0
+            g_views[k] *= m
+    gimg = r.pack([g.astype(np.float32) for g in g_views])
+    g_gpu = new_grads(sc.n, DEV)
+    gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+    r.backward(params, sigma, sc.background, gimg, g_gpu, gsig)
+    torch.cuda.synchronize()
+    # the oracle gets exactly the float32 gradient image the GPU got
+    g_ref, s_ref, s_abs = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras,
+                                       [g.astype(np.float32).astype(np.float64) for g in g_views], windows,
+                                       with_abs=True)
+    fl = grad_floor(g_ref)
+    for name, _ in O.GROUPS:
+        rel, den = grad_rel(to_np(g_gpu[name]), g_ref[name], fl)
+        log(f"  grad {name}: rel {rel:.2e} (norm {den:.3e})")
+        assert rel <= GRAD_RTOL, (name, rel)
+    srel = abs(float(gsig.item()) - s_ref) / max(abs(s_ref), 1e-3 * s_abs, 1e-30)
+    log(f"  grad sigma: gpu {float(gsig.item()):.6e} oracle {s_ref:.6e} (sum |terms| {s_abs:.3e}) rel {srel:.2e}")
+    assert srel <= SIGMA_RTOL or abs(float(gsig.item()) - s_ref) <= sigma_atol
+    return r
+
+
+@pytest.mark.parametrize("tile,batch", [(16, 64), (8, 32), (32, 256), (16, 128)])
+def test_tiny_dense_parity(tile, batch):
+    log(f"tiny dense parity tile={tile} batch={batch}")
+    sc = scenes.make_scene(1)
+    dense_case(sc, tile, batch)
+
+
+def test_ragged_image_and_tiles():
+    log("ragged 100x75 image, 3000 splats")
+    sc = scenes.random_scene(21, 3000, 100, 75, mean_range=1.0)
+    dense_case(sc, 16, 64)
+    dense_case(sc, 32, 64)
+
+
+def test_multiview_uneven_batch():
+    log("multi-view batch of uneven sizes in one launch")
+    sc = scenes.random_scene(22, 1500, 64, 48, n_views=1, mean_range=1.0)
+    cams = [scenes.orbit_camera(3.5, 0.3 * k, 0.1 * k - 0.2, 48 + 24 * k, 40 + 10 * k) for k in range(4)]
+    rng = np.random.default_rng(5)
+    sc.cameras = cams
+    sc.targets = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    dense_case(sc, 16, 64)
+
+
+def test_edge_cases():
+    log("edge cases: one splat; everything behind the camera")
+    sc = scenes.random_scene(23, 1, 32, 32, mean_range=0.0, log_scale_mu=-2.0)
+    # a lone splat has F = c on every pixel, so dL/dw and dL/dsigma vanish exactly; float32
+    # round-off of (c - F) leaves ~1e-10, far below any real sigma gradient (~1e-2 here)
+    dense_case(sc, 8, 32, sigma_atol=1e-8)
+    sc2 = scenes.random_scene(24, 50, 40, 30, mean_range=0.5)
+    sc2.params["mean"][2, :] -= 10.0     # all behind the camera
+    params = params_to_device(sc2.params)
+    sigma = torch.tensor([sc2.sigma], device=DEV)
+    r = Renderer(sc2.cameras, sc2.n, tile=16)
+    r.forward(params, sigma, (0.25, 0.5, 0.75))
+    img = image_views(r, r.image, 3)[0]
+    np.testing.assert_allclose(img[0], 0.25, atol=0)
+    np.testing.assert_allclose(img[2], 0.75, atol=0)
+
+
+def test_dense_config2_full_frame_and_crop_grads():
+    log("config 2: 100k splats, 800x800; full-frame image, 64x64 centre-crop gradients")
+    sc = scenes.make_scene(2)
+    dense_case(sc, 16, 64, windows=[(368, 368, 432, 432)])
+
+
+def test_l1_loss_matches_oracle():
+    sc = scenes.make_scene(1)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n)
+    r.forward(params, sigma, sc.background)
+    tgt = r.pack(sc.targets)
+    gi = torch.zeros_like(r.image)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    oit.l1_loss(r.image, tgt, r.cams_arr, r.n_views, gi, loss, r.ws)
+    torch.cuda.synchronize()
+    L, g = O.l1_loss(to_np(r.image).reshape(3, 128, 128), sc.targets[0])
+    # |C - I| is formed in float32 on the GPU and accumulated in float64
+    assert float(loss.item()) == pytest.approx(L, rel=1e-7)
+    np.testing.assert_array_equal(to_np(gi).reshape(3, 128, 128), g.astype(np.float32).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------------
+# active set
+# ---------------------------------------------------------------------------------
+
+def run_select(score, label, k, mode=0, thresh=0.0, dcap=None):
+    n = score.numel()
+    acap = max(k, 1) if mode == 0 else n
+    dcap = dcap or n
+    idx = torch.zeros(acap, dtype=torch.int32, device=DEV)
+    na = torch.zeros(1, dtype=torch.int32, device=DEV)
+    didx = torch.zeros(dcap, dtype=torch.int32, device=DEV)
+    dsg = torch.zeros(dcap, dtype=torch.int8, device=DEV)
+    nd = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = torch.zeros(oit.select_workspace_bytes(n) + 256, dtype=torch.uint8, device=DEV)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + oit.select_workspace_bytes(n)]
+    oit.update_active_set(score, n, mode, k, thresh, label, idx, na, didx, dsg, nd, ws)
+    torch.cuda.synchronize()
+    a = int(na.item())
+    d = int(nd.item())
+    return idx[:a].cpu().numpy(), didx[:d].cpu().numpy(), dsg[:d].cpu().numpy(), oit.read_status(ws)
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (1000, 37), (5000, 250), (70001, 3500), (300000, 15000), (4096, 4096)])
+def test_topk_selection_bit_exact(n, k):
+    rng = np.random.default_rng(n + k)
+    s = (rng.integers(0, 50, size=n) / 7.0).astype(np.float32)     # heavy ties
+    s[rng.random(n) < 0.2] = 0.0
+    old = (rng.random(n) < 0.3).astype(np.uint8)
+    score = torch.tensor(s, device=DEV)
+    label = torch.tensor(old, device=DEV)
+    idx, didx, dsg, st = run_select(score, label, k)
+    want = O.select_topk(s, k)
+    np.testing.assert_array_equal(idx, want)
+    lab, widx, wsign = O.label_delta(old, want, n)
+    np.testing.assert_array_equal(label.cpu().numpy(), lab)
+    np.testing.assert_array_equal(didx, widx)
+    np.testing.assert_array_equal(dsg, wsign)
+    assert st == 0
+
+
+def test_threshold_selection_bit_exact():
+    rng = np.random.default_rng(3)
+    n = 20000
+    s = rng.exponential(size=n).astype(np.float32)
+    old = (rng.random(n) < 0.5).astype(np.uint8)
+    label = torch.tensor(old, device=DEV)
+    idx, didx, dsg, st = run_select(torch.tensor(s, device=DEV), label, 0, mode=1, thresh=1.0)
+    want = O.select_threshold(s.astype(np.float64), 1.0)
+    np.testing.assert_array_equal(idx, want)
+    _, widx, wsign = O.label_delta(old, want, n)
+    np.testing.assert_array_equal(didx, widx)
+    np.testing.assert_array_equal(dsg, wsign)
+
+
+def test_selection_overflow_sets_status():
+    n = 1000
+    s = np.linspace(0, 1, n).astype(np.float32)
+    label = torch.zeros(n, dtype=torch.uint8, device=DEV)
+    idx, didx, dsg, st = run_select(torch.tensor(s, device=DEV), label, 500, dcap=100)
+    assert st & oit.STATUS_DELTA_OVERFLOW
+    assert len(didx) == 100
+    np.testing.assert_array_equal(didx, np.arange(500, 600))
+
+
+def test_sparse_adam_matches_oracle():
+    rng = np.random.default_rng(9)
+    n = 5000
+    rows = np.sort(rng.choice(n, size=700, replace=False))
+    params = {g: torch.tensor(rng.normal(size=(c, n)), dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
+    m = {g: torch.tensor(rng.normal(size=(c, n)) * 0.01, dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
+    v = {g: torch.tensor(rng.random(size=(c, n)) * 0.01, dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
+    ref = {g: (to_np(params[g]).copy(), to_np(m[g]).copy(), to_np(v[g]).copy()) for g, _ in O.GROUPS}
+    acap = 1024
+    grads = {g: torch.zeros((c, acap), device=DEV) for g, c in O.GROUPS}
+    gv = {g: rng.normal(size=(c, len(rows))).astype(np.float32) for g, c in O.GROUPS}
+    for g, _ in O.GROUPS:
+        grads[g][:, :len(rows)] = torch.tensor(gv[g], device=DEV)
+    idx = torch.zeros(acap, dtype=torch.int32, device=DEV)
+    idx[:len(rows)] = torch.tensor(rows, dtype=torch.int32, device=DEV)
+    na = torch.tensor([len(rows)], dtype=torch.int32, device=DEV)
+    step = torch.tensor([4], dtype=torch.int32, device=DEV)
+    lr = [1e-3, 2e-3, 3e-3, 1e-2, 5e-3, 5e-3]
+    oit.sparse_adam_step(params, oit.grads_struct(grads, acap), m, v, idx, na, n, lr, 0.9, 0.999, 1e-15, step)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 5
+    f32 = lambda x: float(np.float32(x))    # the kernel receives float32 hyper-parameters
+    for k, (g, _) in enumerate(O.GROUPS):
+        p0, m0, v0 = ref[g]
+        O.adam_rows(p0, gv[g].astype(np.float64), m0, v0, rows, f32(lr[k]), f32(0.9), f32(0.999), f32(1e-15), 5)
+        np.testing.assert_allclose(to_np(params[g]), p0, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(to_np(m[g]), m0, rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(to_np(v[g]), v0, rtol=1e-5, atol=1e-9)
+
+
+def test_sparse_adam_leaves_inactive_rows_bitwise():
+    rng = np.random.default_rng(10)
+    n = 3000
+    rows = np.sort(rng.choice(n, size=300, replace=False))
+    params = {g: torch.tensor(rng.normal(size=(c, n)), dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
+    m = {g: torch.zeros((c, n), device=DEV) for g, c in O.GROUPS}
+    v = {g: torch.zeros((c, n), device=DEV) for g, c in O.GROUPS}
+    before = {g: params[g].clone() for g, _ in O.GROUPS}
+    grads = {g: torch.ones((c, 300), device=DEV) for g, c in O.GROUPS}
+    idx = torch.tensor(rows, dtype=torch.int32, device=DEV)
+    na = torch.tensor([300], dtype=torch.int32, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    oit.sparse_adam_step(params, oit.grads_struct(grads, 300), m, v, idx, na, n, [1e-3] * 6, 0.9, 0.999, 1e-15,
+                         step)
+    torch.cuda.synchronize()
+    keep = torch.tensor(np.setdiff1d(np.arange(n), rows), device=DEV)
+    for g, _ in O.GROUPS:
+        assert torch.equal(params[g][:, keep], before[g][:, keep])
+        assert torch.equal(m[g][:, keep], torch.zeros_like(m[g][:, keep]))
+        assert not torch.equal(params[g][:, idx.long()], before[g][:, idx.long()])
+
+
+def test_active_set_render_equals_dense():
+    """Active splats rendered against the pre-rendered inactive set give the dense image
+    and, on the active rows, the dense gradients (Sec. 4.1)."""
+    log("active set vs dense, 2 views")
+    sc = scenes.random_scene(31, 4000, 96, 80, n_views=2, mean_range=1.0)
+    n = sc.n
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    rng = np.random.default_rng(31)
+    total_px = sum(c.width * c.height for c in sc.cameras)
+    # step 1: every splat active (pre empty); step 2: top-k of random scores
+    k = 900
+    label = torch.ones(n, dtype=torch.uint8, device=DEV)
+    score = torch.tensor(rng.random(n).astype(np.float32), device=DEV)
+    idx, didx, dsg, st = run_select(score, label, k)
+    act = {"idx": torch.tensor(idx, dtype=torch.int32, device=DEV),
+           "n": torch.tensor([len(idx)], dtype=torch.int32, device=DEV),
+           "delta_idx": torch.tensor(didx, dtype=torch.int32, device=DEV),
+           "delta_sign": torch.tensor(dsg, dtype=torch.int8, device=DEV),
+           "n_delta": torch.tensor([len(didx)], dtype=torch.int32, device=DEV)}
+    pre = torch.zeros(9 * total_px, device=DEV)
+    r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=len(didx), tile=16)
+    r.fit_pair_capacity(params, sigma, sc.background, act, pre)
+    r.forward(params, sigma, sc.background, act, pre)
+    torch.cuda.synchronize()
+    assert r.status() == 0
+    imgs = image_views(r, r.image, 3)
+    pres = image_views(r, pre, 9)
+    inactive = np.ones(n, bool)
+    inactive[idx] = False
+    for v, cam in enumerate(sc.cameras):
+        dense = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)
+        err = compare_image(imgs[v], dense["image"], dense["near"])
+        log(f"  view {v}: active-set image vs dense oracle err {err:.2e}")
+        assert err <= IMAGE_RTOL
+        ref_pre = O.render(sc.params, sc.sigma, sc.background, cam, include=inactive.astype(np.uint8))["pre"]
+        ok = ~dense["near"]
+        for p in range(9):
+            rel = np.abs(pres[v][p][ok] - ref_pre[p][ok]).max() / max(np.abs(ref_pre[p]).max(), 1e-30)
+            assert rel < 1e-4, (v, p, rel)
+    # gradients on the active rows equal the dense gradients restricted to A
+    g_views = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cameras]
+    gimg = r.pack(g_views)
+    g_gpu = new_grads(k, DEV)
+    gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+    r.backward(params, sigma, sc.background, gimg, g_gpu, gsig, act, pre)
+    torch.cuda.synchronize()
+    g_ref, s_ref = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras,
+                                [g.astype(np.float64) for g in g_views])
+    fl = grad_floor({k: v[:, idx] for k, v in g_ref.items()})
+    for name, _ in O.GROUPS:
+        rel, _ = grad_rel(to_np(g_gpu[name])[:, :len(idx)], g_ref[name][:, idx], fl)
+        log(f"  active grad {name}: rel {rel:.2e}")
+        assert rel <= GRAD_RTOL
+    srel = abs(float(gsig.item()) - s_ref) / abs(s_ref)
+    log(f"  sigma (active + pre part) rel {srel:.2e}")
+    assert srel <= SIGMA_RTOL
+
+    # step 3: a new selection; the label changes move splats in and out of pre
+    score2 = torch.tensor(rng.random(n).astype(np.float32), device=DEV)
+    idx2, didx2, dsg2, _ = run_select(score2, label, k)
+    act2 = {"idx": torch.tensor(idx2, dtype=torch.int32, device=DEV),
+            "n": torch.tensor([len(idx2)], dtype=torch.int32, device=DEV),
+            "delta_idx": torch.tensor(didx2, dtype=torch.int32, device=DEV),
+            "delta_sign": torch.tensor(dsg2, dtype=torch.int8, device=DEV),
+            "n_delta": torch.tensor([len(didx2)], dtype=torch.int32, device=DEV)}
+    r2 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=16)
+    r2.fit_pair_capacity(params, sigma, sc.background, act2, pre)
+    r2.forward(params, sigma, sc.background, act2, pre)
+    imgs2 = image_views(r2, r2.image, 3)
+    for v, cam in enumerate(sc.cameras):
+        dense = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)
+        err = compare_image(imgs2[v], dense["image"], dense["near"])
+        log(f"  after label changes, view {v}: err {err:.2e}")
+        assert err <= IMAGE_RTOL
+
+
+def test_pair_overflow_is_reported_and_bounded():
+    sc = scenes.make_scene(1)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n, tile=16, pair_capacity=100)
+    r.forward(params, sigma, sc.background)
+    torch.cuda.synchronize()
+    assert r.status() & oit.STATUS_PAIR_OVERFLOW
+    need = r.pairs_needed()
+    assert need > 100
+    r.set_tuning(pair_capacity=need)
+    r.forward(params, sigma, sc.background)
+    assert r.status() == 0
+
+
+def test_autograd_matches_oracle_finite_differences():
+    """OITRender's backward against FP64 central differences of the oracle forward."""
+    log("autograd vs oracle finite differences")
+    sc = scenes.random_scene(41, 40, 40, 32, mean_range=0.4, log_scale_mu=-2.5)
+    params = {g: t.requires_grad_(True) for g, t in params_to_device(sc.params).items()}
+    sigma = torch.tensor([sc.sigma], device=DEV, requires_grad=True)
+    r = Renderer(sc.cameras, sc.n, tile=8, batch=32)
+    rng = np.random.default_rng(41)
+    gw = rng.normal(size=(3, 32, 40))
+    img = render(r, sigma, params, sc.background)
+    loss = (img * torch.tensor(gw.reshape(-1), dtype=torch.float32, device=DEV)).sum()
+    loss.backward()
+    cam = sc.cameras[0]
+    base = O.render(sc.params, sc.sigma, sc.background, cam)
+
+    def L(p, s=sc.sigma):
+        rr = O.render(p, s, sc.background, cam)
+        return float((gw * rr["image"]).sum()), rr["signature"]
+
+    checked = 0
+    for name, ncomp in O.GROUPS:
+        an = to_np(params[name].grad)
+        picks = [(c, i) for c in range(ncomp) for i in range(sc.n)]
+        rng.shuffle(picks)
+        num = den = 0.0
+        for c, i in picks[:40]:
+            p = {k: v.astype(np.float64).copy() for k, v in sc.params.items()}
+            x0 = p[name][c, i]
+            h = 1e-6 * max(1.0, abs(x0))
+            p[name][c, i] = x0 + h
+            lp, sp = L(p)
+            p[name][c, i] = x0 - h
+            lm, sm = L(p)
+            if sp != base["signature"] or sm != base["signature"]:
+                continue
+            fd = (lp - lm) / (2 * h)
+            num += (an[c, i] - fd) ** 2
+            den += fd ** 2
+            checked += 1
+        rel = math.sqrt(num) / max(math.sqrt(den), 1e-30)
+        log(f"  {name}: autograd vs FD rel {rel:.2e}")
+        assert rel <= 1e-3
+    h = 1e-6 * sc.sigma
+    fd = (L(sc.params, sc.sigma + h)[0] - L(sc.params, sc.sigma - h)[0]) / (2 * h)
+    assert float(sigma.grad.item()) == pytest.approx(fd, rel=1e-3, abs=1e-8)
+    assert checked > 100
+
+
+def test_graph_replays_match_eager():
+    """A captured active-set iteration replayed several times gives the same state as
+    the same iterations run eagerly."""
+    log("hipGraph replay vs eager")
+    sc = scenes.random_scene(51, 3000, 64, 48, n_views=2, mean_range=1.0)
+
+    def make():
+        t = ActiveSetTrainer(sc, fraction=0.2, tile=16)
+        t.warmup_dense_scores()
+        return t
+
+    eager = make()
+    graphed = make()
+    for _ in range(1):
+        eager.iteration()
+    graphed.capture()          # runs one eager warm-up iteration, then captures
+    for it in range(3):
+        eager.iteration()
+        graphed.replay()
+        torch.cuda.synchronize()
+        # some unrelated eager work between replays
+        _ = (torch.randn(1000, device=DEV) * 2).sum().item()
+        for g, _ in O.GROUPS:
+            np.testing.assert_allclose(to_np(graphed.params[g]), to_np(eager.params[g]), rtol=1e-5, atol=1e-6)
+        assert float(graphed.loss.item()) == pytest.approx(float(eager.loss.item()), rel=1e-5)
+        log(f"  replay {it}: loss {float(graphed.loss.item()):.6f}")
