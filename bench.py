@@ -1,0 +1,276 @@
+#!/usr/bin/env python
+"""Benchmark of one SparseOIT training iteration on one MI355X.
+
+Workload (default): 1,000,000 splats, 16 views of uneven size (640x480 .. 1600x1200)
+on an orbit of radius 4, 5% of the splats active (top-k of the activeness score every
+step), L1 loss, sparse Adam.  One step = active-set selection + forward (projection,
+tile binning, blend-and-normalise with the pre-rendered inactive set and its update)
++ loss + backward + sparse Adam + Adam on sigma, captured once as a HIP graph and
+replayed.  The dense full-set form of the same iteration is measured beside it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, 256 CUs x 2.4 GHz x 256 flop/clk
+PEAK_HBM_GBS = 8000.0
+# algorithmic flops per (splat, pixel) pair; counted in the design doc
+FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 10, 12
+BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 10, 39
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def prime(trainer):
+    """First iteration, eager: selection, pair-capacity fit, then the full step."""
+    from paper_2605_13855_amd import oit
+    if not trainer.dense:
+        trainer.select()
+        trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg, trainer._active(), trainer.pre)
+    else:
+        trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg)
+    trainer.forward_loss()
+    trainer.backward()
+    trainer.optimise()
+    st = trainer.r.status()
+    if st & oit.STATUS_PAIR_OVERFLOW:
+        raise RuntimeError("pair capacity overflow after fitting")
+
+
+def time_eager(trainer, iters=3):
+    import torch
+    ts = []
+    for _ in range(iters):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        trainer.iteration()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
+def autotune(trainer, tiles=(8, 16, 32), batches=(32, 64, 128, 256), iters=3):
+    """Pick tile size and LDS batch by timing whole eager iterations on the live state."""
+    results = {}
+    for tile in tiles:
+        for batch in batches:
+            trainer.r.set_tuning(tile=tile, batch=batch)
+            if not trainer.dense:
+                trainer.select()
+                trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg, trainer._active(),
+                                            trainer.pre)
+                trainer.forward_loss()
+                trainer.backward()
+                trainer.optimise()
+            else:
+                trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg)
+            ms = time_eager(trainer, iters)
+            results[(tile, batch)] = ms
+            log(f"  autotune tile={tile:2d} batch={batch:3d}: {ms:8.3f} ms/iter")
+    best = min(results, key=results.get)
+    return best, results
+
+
+def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune):
+    import torch
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd.render import ActiveSetTrainer
+
+    name = "dense" if dense else f"active {fraction:.0%}"
+    log(f"{name}: building trainer")
+    t = ActiveSetTrainer(scene, fraction=fraction, tile=tile, batch=batch, dense=dense)
+    if not dense:
+        t.warmup_dense_scores()
+    prime(t)
+    tuned = None
+    if tune:
+        (bt, bb), res = autotune(t)
+        tuned = {"tile": bt, "batch": bb, "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in res.items()}}
+        t.r.set_tuning(tile=bt, batch=bb)
+        prime(t)
+    # headroom for the tile lists of later steps (the active set moves)
+    need = t.r.pairs_needed()
+    t.r.set_tuning(pair_capacity=min(int(need * 1.5) + 65536, 2 ** 32 - 2))
+    log(f"{name}: tile={t.r.tuning.tile} batch={t.r.tuning.batch} pair_capacity={t.r.tuning.pair_capacity}")
+    oit.timing_enable(True)
+    t.capture()
+    for _ in range(warmup):
+        t.replay()
+    torch.cuda.synchronize()
+    oit.clear_status(t.r.ws)
+    log(f"{name}: timing {steps} graph replays")
+    step_ms, fwd_ms, bwd_ms, pairs, evals = [], [], [], [], []
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        t.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        step_ms.append(e0.elapsed_time(e1))
+        f, b = oit.timing_read()
+        fwd_ms.append(f)
+        bwd_ms.append(b)
+        c = t.r.counters()
+        pairs.append(c[1])
+        evals.append(c[2])
+    torch.cuda.synchronize()
+    oit.timing_enable(False)
+    st = t.r.status()
+    if st:
+        raise RuntimeError(f"device status {st} during the timed steps")
+    loss = float(t.loss.item())
+    n_active = t.k
+    out = {
+        "ms_per_step": statistics.mean(step_ms),
+        "ms_per_step_median": statistics.median(step_ms),
+        "raster_fwd_ms": statistics.mean(fwd_ms),
+        "raster_bwd_ms": statistics.mean(bwd_ms),
+        "pairs": statistics.mean(pairs),
+        "evals": statistics.mean(evals),
+        "loss": loss,
+        "active": n_active,
+        "tile": t.r.tuning.tile,
+        "batch": t.r.tuning.batch,
+        "tuned": tuned,
+    }
+    log(f"{name}: {out['ms_per_step']:.3f} ms/step (raster fwd {out['raster_fwd_ms']:.3f} ms, "
+        f"bwd {out['raster_bwd_ms']:.3f} ms), {out['pairs']:.3e} contributing pairs")
+    del t
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(scene, budget_s=20.0):
+    """The FP64 oracle, single-threaded, on a window of view 0 (all splats), fwd + bwd."""
+    import numpy as np
+    from oracle import oracle as O
+    cam = scene.cameras[0]
+    side = 48
+    cx, cy = cam.width // 2, cam.height // 2
+    rng = np.random.default_rng(0)
+    total_pairs, total_s = 0, 0.0
+    while True:
+        win = (cx - side // 2, cy - side // 2, cx + side // 2, cy + side // 2)
+        t0 = time.perf_counter()
+        r = O.render(scene.params, scene.sigma, scene.background, cam, window=win)
+        g = np.zeros((3, cam.height, cam.width))
+        g[:, win[1]:win[3], win[0]:win[2]] = rng.normal(size=(3, side, side))
+        O.backward(scene.params, scene.sigma, scene.background, cam, g, window=win)
+        dt = time.perf_counter() - t0
+        total_pairs, total_s = r["pairs"], dt
+        log(f"cpu oracle: window {side}x{side}: {r['pairs']:.3e} pairs, {dt:.2f} s")
+        if dt > budget_s / 4 or side >= 512:
+            break
+        side = min(512, int(side * math.sqrt(budget_s / 2 / max(dt, 1e-3))))
+    return {"value": total_pairs / total_s, "unit": "splat-pixel evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle fwd+bwd, view 0 ({cam.width}x{cam.height}), all "
+                      f"{scene.n} splats, centre window {side}x{side}: {total_pairs} contributing pairs "
+                      f"in {total_s:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--fraction", type=float, default=0.05)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--log-scale-mu", type=float, default=-3.5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
+              f"described, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_13855_amd import oit  # noqa: F401  (fails loudly without the HIP library)
+    from paper_2605_13855_amd import scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"building scene config {args.config}")
+    scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
+    px = sum(c.width * c.height for c in scene.cameras)
+    log(f"scene: {scene.n} splats, {len(scene.cameras)} views, {px} pixels")
+
+    act = run_form(scene, False, args.steps, args.warmup, args.fraction, args.tile, args.batch,
+                   not args.no_autotune)
+    dense = None
+    if not args.no_dense:
+        dense = run_form(scene, True, max(3, args.steps // 4), max(1, args.warmup // 2), 1.0, act["tile"],
+                         act["batch"], False)
+
+    # dominant kernel of the active step, roofline against the FP32 vector peak
+    fwd_flops = act["evals"] * FWD_FLOP_EVAL + act["pairs"] * FWD_FLOP_CONTRIB
+    bwd_flops = act["evals"] * BWD_FLOP_EVAL + act["pairs"] * BWD_FLOP_CONTRIB
+    if act["raster_bwd_ms"] >= act["raster_fwd_ms"]:
+        kname, kms, kflops = "k_raster_bwd", act["raster_bwd_ms"], bwd_flops
+    else:
+        kname, kms, kflops = "k_raster_fwd", act["raster_fwd_ms"], fwd_flops
+    achieved = kflops / (kms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": kflops, "avg_launch_ms": round(kms, 4)}
+    cpu = None if args.no_cpu else cpu_baseline(scene)
+
+    value = act["pairs"] / (act["ms_per_step"] * 1e-3)
+    line = {
+        "metric": "fwd+bwd ms/iter and splat-pixel evals/s, active-set vs dense, 1M splats",
+        "value": value,
+        "unit": "splat-pixel evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(act["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"config {args.config}: {scene.n} splats, {len(scene.cameras)} views "
+                        f"({px} px, uneven 640x480..1600x1200), {args.fraction:.0%} active top-k each step, "
+                        f"hipGraph iteration, L1 + sparse Adam",
+            "splats": scene.n, "views": len(scene.cameras), "pixels": px, "active_fraction": args.fraction,
+            "tile": act["tile"], "batch": act["batch"], "log_scale_mu": args.log_scale_mu,
+        },
+        "active": {"ms_per_step": round(act["ms_per_step"], 4), "ms_median": round(act["ms_per_step_median"], 4),
+                   "evals_per_s": value, "contributing_pairs": act["pairs"], "evaluated_pairs": act["evals"],
+                   "raster_fwd_ms": round(act["raster_fwd_ms"], 4), "raster_bwd_ms": round(act["raster_bwd_ms"], 4),
+                   "loss": act["loss"], "autotune": act["tuned"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if dense is not None:
+        line["dense"] = {"ms_per_step": round(dense["ms_per_step"], 4),
+                         "evals_per_s": dense["pairs"] / (dense["ms_per_step"] * 1e-3),
+                         "contributing_pairs": dense["pairs"], "evaluated_pairs": dense["evals"],
+                         "raster_fwd_ms": round(dense["raster_fwd_ms"], 4),
+                         "raster_bwd_ms": round(dense["raster_bwd_ms"], 4)}
+        line["speedup_active_vs_dense"] = round(dense["ms_per_step"] / act["ms_per_step"], 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -242,14 +242,30 @@ oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m,
 oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream);
 
 /*
- * Wait for `stream` and report the number of (tile, splat) entries the last
- * oit_render_fwd on this workspace needed (also when it overflowed
- * tuning.pair_capacity), so that a caller can size pair_capacity and run again.
- * Arguments as given to that oit_render_fwd; *out (host).
+ * Wait for `stream` and copy the counters the last oit_render_fwd on this workspace
+ * left (arguments as given to that call; out (host) [4]):
+ *   out[0] (tile, splat) entries it needed (also when it overflowed tuning.pair_capacity,
+ *          so a caller can size pair_capacity and run again),
+ *   out[1] contributing (alpha >= 1/255) active (splat, pixel) pairs it blended,
+ *   out[2] active (splat, pixel) pairs it evaluated (tile entries x in-image tile pixels),
+ *   out[3] backward work items (64 active entries of one tile each).
  */
-oit_status oit_read_pair_total(const void *ws, size_t ws_bytes, const oit_capacity *cap,
-                               const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,
-                               int64_t *out, oit_stream stream);
+oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity *cap,
+                             const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,
+                             int64_t *out, oit_stream stream);
+
+/*
+ * Timing of the two raster kernels, for benchmarks.  While enabled (on != 0), every
+ * oit_render_fwd records a pair of HIP events around its raster kernel and every
+ * oit_render_bwd around its raster kernel, on the call's stream (also when captured
+ * in a graph).  The events are created once by the first enable and owned by the
+ * library; the setting is process-wide and not synchronised between threads.
+ */
+oit_status oit_timing_enable(int32_t on);
+
+/* Wait for the last recorded events; out (host) [2] = milliseconds of the last
+ * forward and backward raster kernel (-1 if not recorded). */
+oit_status oit_timing_read(float *out);
 
 /* Clear the status word (enqueued on `stream`). */
 oit_status oit_clear_status(void *ws, size_t ws_bytes, oit_stream stream);

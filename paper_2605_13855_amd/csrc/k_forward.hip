@@ -337,6 +337,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
 
     float px[PPT], py[PPT];
     float P[PPT][3], Q[PPT], T[PPT];
+    uint32_t npair[PPT];   // contributing active pairs per pixel (throughput counter)
     float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -349,6 +350,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
         dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
         dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
         dQ0[p] = dQ1[p] = dL[p] = 0.f;
+        npair[p] = 0;
     }
 
     const uint64_t cap = (uint64_t)a.b.pair_cap;
@@ -384,6 +386,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                     P[p][2] = fmaf(rc.x, aw, P[p][2]);
                     Q[p] += aw;
                     T[p] *= 1.f - al;
+                    ++npair[p];
                 }
             }
         }
@@ -421,6 +424,25 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                     dL[p] = fmaf(rc.w, logf(1.f - al), dL[p]);
                 }
             }
+        }
+    }
+
+    // throughput counters: contributing active pairs and evaluated (in-image) pairs
+    {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p)
+            if ((int)px[p] < cam.W && (int)py[p] < cam.H) c += npair[p];
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        __shared__ unsigned long long s_cnt[NT / 64 > 0 ? NT / 64 : 1];
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < (NT + 63) / 64; ++w) t += s_cnt[w];
+            const int inside = min(S, cam.W - tx * S) * min(S, cam.H - ty * S);
+            if (t) atomicAdd((unsigned long long *)(a.b.counters + CNT_PAIRS), t);
+            if (na) atomicAdd((unsigned long long *)(a.b.counters + CNT_EVAL), (unsigned long long)na * inside);
         }
     }
 

@@ -14,6 +14,11 @@ namespace {
 
 thread_local char g_err[512] = "";
 
+// optional timing of the two raster kernels (see oit_timing_enable)
+hipEvent_t g_ev[4];
+bool g_timing_ready = false;
+bool g_timing_on = false;
+
 oit_status fail(oit_status st, const char *fmt, ...)
 {
     va_list ap;
@@ -261,11 +266,14 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.cnt_a, 4 * (size_t)p.T, 0u, s);
+    fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
     launch_preprocess_count(splat_ptrs(splats), sigma, rl, b, s);
     launch_scan_tiles(b, s);
     launch_emit(rl, b, s);
+    if (g_timing_on) hipEventRecord(g_ev[0], s);
     if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
+    if (g_timing_on) hipEventRecord(g_ev[1], s);
     return check_launch("oit_render_fwd");
 }
 
@@ -330,7 +338,9 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     fill_u32(b.counters + CNT_BWD_WORK, 1, 0u, s);
     fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
+    if (g_timing_on) hipEventRecord(g_ev[2], s);
     if (!launch_raster_bwd(b, rl, s)) return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
+    if (g_timing_on) hipEventRecord(g_ev[3], s);
     launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
     return check_launch("oit_render_bwd");
 }
@@ -428,19 +438,47 @@ oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_st
     return ok();
 }
 
-oit_status oit_read_pair_total(const void *ws, size_t ws_bytes, const oit_capacity *cap, const oit_camera *cams,
-                               int32_t n_views, const oit_tuning *tuning, int64_t *out, oit_stream stream)
+oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity *cap, const oit_camera *cams,
+                             int32_t n_views, const oit_tuning *tuning, int64_t *out, oit_stream stream)
 {
     Plan p;
     oit_status st;
     if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
-    if (!ws || !out || ws_bytes < p.total) return fail(OIT_ERR_INVALID, "oit_read_pair_total: bad arguments");
-    uint32_t v = 0;
-    const char *src = (const char *)ws + p.counters + 4 * CNT_TOTAL_ENTRIES;
-    hipError_t e = hipMemcpyAsync(&v, src, 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (!ws || !out || ws_bytes < p.total) return fail(OIT_ERR_INVALID, "oit_read_counters: bad arguments");
+    uint32_t v[CNT_SLOTS];
+    hipError_t e = hipMemcpyAsync(v, (const char *)ws + p.counters, sizeof(v), hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_read_pair_total: %s", hipGetErrorString(e));
-    *out = (int64_t)v;
+    if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_read_counters: %s", hipGetErrorString(e));
+    out[0] = (int64_t)v[CNT_TOTAL_ENTRIES];
+    out[1] = (int64_t)((uint64_t)v[CNT_PAIRS] | ((uint64_t)v[CNT_PAIRS + 1] << 32));
+    out[2] = (int64_t)((uint64_t)v[CNT_EVAL] | ((uint64_t)v[CNT_EVAL + 1] << 32));
+    out[3] = (int64_t)v[CNT_TOTAL_CHUNKS];
+    return ok();
+}
+
+oit_status oit_timing_enable(int32_t on)
+{
+    if (on && !g_timing_ready) {
+        for (int k = 0; k < 4; ++k) {
+            const hipError_t e = hipEventCreate(&g_ev[k]);
+            if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_timing_enable: %s", hipGetErrorString(e));
+        }
+        g_timing_ready = true;
+    }
+    g_timing_on = on != 0;
+    return ok();
+}
+
+oit_status oit_timing_read(float *out)
+{
+    if (!out) return fail(OIT_ERR_INVALID, "oit_timing_read: NULL output");
+    if (!g_timing_ready) return fail(OIT_ERR_INVALID, "oit_timing_read: timing was never enabled");
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipEventSynchronize(g_ev[2 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&out[k], g_ev[2 * k], g_ev[2 * k + 1]);
+        if (e != hipSuccess) out[k] = -1.f;
+    }
     return ok();
 }
 

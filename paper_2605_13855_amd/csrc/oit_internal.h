@@ -14,7 +14,8 @@ constexpr int kBwdLanes = 64;   // splats per backward work item (one wave)
 constexpr int kScanThreads = 1024;
 
 // counters[] slots in the workspace
-enum { CNT_BWD_WORK = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SLOTS = 16 };
+// (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
+enum { CNT_BWD_WORK = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_SLOTS = 16 };
 
 struct SplatPtrs {
     const float *mean, *log_scale, *quat, *logit, *sh, *vsh;

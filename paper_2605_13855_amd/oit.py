@@ -72,12 +72,14 @@ def _load():
     L.oit_sigma_adam_step.argtypes = [P, P, P, P, F, F, F, F, P, P]
     L.oit_read_status.argtypes = [P, SZ, P, P]
     L.oit_clear_status.argtypes = [P, SZ, P]
-    L.oit_read_pair_total.argtypes = [P, SZ, P, P, I32, P, P, P]
+    L.oit_read_counters.argtypes = [P, SZ, P, P, I32, P, P, P]
+    L.oit_timing_enable.argtypes = [I32]
+    L.oit_timing_read.argtypes = [P]
     L.oit_last_error.argtypes = []
     L.oit_last_error.restype = ctypes.c_char_p
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
-              L.oit_read_pair_total):
+              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read):
         f.restype = ctypes.c_int
     return L
 
@@ -207,12 +209,24 @@ def read_status(ws, stream=None) -> int:
     return int(out.value)
 
 
-def read_pair_total(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, stream=None) -> int:
-    out = ctypes.c_int64(0)
-    rc = lib.oit_read_pair_total(_ptr(ws), ws.numel(), ctypes.byref(cap), cams_arr, n_views, ctypes.byref(tuning),
-                                 ctypes.byref(out), _stream(stream))
-    _check(rc, "oit_read_pair_total")
-    return int(out.value)
+def read_counters(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, stream=None):
+    """(entries needed, contributing pairs, evaluated pairs, backward work items) of the
+    last forward on this workspace."""
+    out = (ctypes.c_int64 * 4)()
+    rc = lib.oit_read_counters(_ptr(ws), ws.numel(), ctypes.byref(cap), cams_arr, n_views, ctypes.byref(tuning),
+                               out, _stream(stream))
+    _check(rc, "oit_read_counters")
+    return tuple(int(x) for x in out)
+
+
+def timing_enable(on: bool):
+    _check(lib.oit_timing_enable(1 if on else 0), "oit_timing_enable")
+
+
+def timing_read():
+    out = (ctypes.c_float * 2)()
+    _check(lib.oit_timing_read(out), "oit_timing_read")
+    return float(out[0]), float(out[1])
 
 
 def clear_status(ws, stream=None):

@@ -36,11 +36,12 @@ def _aligned_workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def estimate_pairs(n_listed: int, cams, tile: int, log_scale_mu=-3.5, depth=3.0) -> int:
-    """Rough (tile, splat) entry estimate used to size the first pair capacity."""
+    """Rough (tile, splat) entry estimate used to size the first pair capacity (the
+    forward reports the exact need, see Renderer.fit_pair_capacity)."""
     tot = 0.0
     for c in cams:
         f = float(c.fx)
-        r = 3.3 * f * math.exp(log_scale_mu + 0.5) / depth + 1.0       # footprint radius, px
+        r = 3.3 * f * math.exp(log_scale_mu) / depth + 1.0       # footprint radius, px
         tiles = (2 * r / tile + 1.5) ** 2
         tot += n_listed * min(tiles, (c.width / tile + 1) * (c.height / tile + 1))
     return int(tot * 1.5) + 4096
@@ -113,8 +114,11 @@ class Renderer:
     def status(self) -> int:
         return oit.read_status(self.ws)
 
+    def counters(self):
+        return oit.read_counters(self.ws, self.cap, self.cams_arr, self.n_views, self.tuning)
+
     def pairs_needed(self) -> int:
-        return oit.read_pair_total(self.ws, self.cap, self.cams_arr, self.n_views, self.tuning)
+        return self.counters()[0]
 
     def fit_pair_capacity(self, params, sigma, bg, active=None, pre=None, slack=1.25):
         """Run the forward once; grow the pair capacity if the tile lists overflowed."""
