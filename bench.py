@@ -50,42 +50,7 @@ def prime(trainer):
         raise RuntimeError("pair capacity overflow after fitting")
 
 
-def time_eager(trainer, iters=3):
-    import torch
-    ts = []
-    for _ in range(iters):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        trainer.iteration()
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    return statistics.median(ts)
-
-
-def autotune(trainer, tiles=(8, 16, 32), batches=(32, 64, 128, 256), iters=3):
-    """Pick tile size and LDS batch by timing whole eager iterations on the live state."""
-    results = {}
-    for tile in tiles:
-        for batch in batches:
-            trainer.r.set_tuning(tile=tile, batch=batch)
-            if not trainer.dense:
-                trainer.select()
-                trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg, trainer._active(),
-                                            trainer.pre)
-                trainer.forward_loss()
-                trainer.backward()
-                trainer.optimise()
-            else:
-                trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg)
-            ms = time_eager(trainer, iters)
-            results[(tile, batch)] = ms
-            log(f"  autotune tile={tile:2d} batch={batch:3d}: {ms:8.3f} ms/iter")
-    best = min(results, key=results.get)
-    return best, results
-
-
-def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune):
+def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=False):
     import torch
     from paper_2605_13855_amd import oit
     from paper_2605_13855_amd.render import ActiveSetTrainer
@@ -98,18 +63,19 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune):
     prime(t)
     tuned = None
     if tune:
-        (bt, bb), res = autotune(t)
+        from paper_2605_13855_amd.autotune import autotune
+        (bt, bb), res = autotune(t, log=log)
         tuned = {"tile": bt, "batch": bb, "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in res.items()}}
-        t.r.set_tuning(tile=bt, batch=bb)
-        prime(t)
     # headroom for the tile lists of later steps (the active set moves)
     need = t.r.pairs_needed()
     t.r.set_tuning(pair_capacity=min(int(need * 1.5) + 65536, 2 ** 32 - 2))
     log(f"{name}: tile={t.r.tuning.tile} batch={t.r.tuning.batch} pair_capacity={t.r.tuning.pair_capacity}")
     oit.timing_enable(True)
-    t.capture()
+    step = t.iteration if eager else t.replay
+    if not eager:
+        t.capture()
     for _ in range(warmup):
-        t.replay()
+        step()
     torch.cuda.synchronize()
     oit.clear_status(t.r.ws)
     log(f"{name}: timing {steps} graph replays")
@@ -118,7 +84,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune):
     for _ in range(steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        t.replay()
+        step()
         e1.record()
         torch.cuda.synchronize()
         step_ms.append(e0.elapsed_time(e1))
@@ -196,6 +162,9 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log-scale-mu", type=float, default=-3.5)
+    ap.add_argument("--eager", action="store_true", help="launch every step eagerly instead of a HIP graph")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
@@ -209,17 +178,25 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_mb:
+        nel = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_mb} MiB read + {args.copy_mb} MiB written")
+        del src, dst
     log(f"building scene config {args.config}")
     scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
     px = sum(c.width * c.height for c in scene.cameras)
     log(f"scene: {scene.n} splats, {len(scene.cameras)} views, {px} pixels")
 
     act = run_form(scene, False, args.steps, args.warmup, args.fraction, args.tile, args.batch,
-                   not args.no_autotune)
+                   not args.no_autotune, args.eager)
     dense = None
     if not args.no_dense:
         dense = run_form(scene, True, max(3, args.steps // 4), max(1, args.warmup // 2), 1.0, act["tile"],
-                         act["batch"], False)
+                         act["batch"], False, args.eager)
 
     # dominant kernel of the active step, roofline against the FP32 vector peak
     fwd_flops = act["evals"] * FWD_FLOP_EVAL + act["pairs"] * FWD_FLOP_CONTRIB
@@ -247,6 +224,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "launch": "eager" if args.eager else "hipGraph",
         "data": "synthetic",
         "config": {
             "workload": f"config {args.config}: {scene.n} splats, {len(scene.cameras)} views "

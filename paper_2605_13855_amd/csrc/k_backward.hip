@@ -201,6 +201,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a)
         float g_mx = 0.f, g_my = 0.f, g_qa = 0.f, g_qb = 0.f, g_qc = 0.f, g_lo = 0.f;
         float g_cr = 0.f, g_cg = 0.f, g_cb = 0.f, g_w = 0.f;
         const size_t pb = (size_t)cam.pix_base;
+        const int cols = min(S, cam.W - tx * S);   // in-image columns of this tile
 
         for (int grp = 0; grp < GROUPS; ++grp) {
             const float gy0 = (float)(ty * S + grp * ROWS) + 0.5f;
@@ -221,34 +222,46 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a)
                 s_pc[wave][lane][1] = c1;
             }
             __builtin_amdgcn_wave_barrier();
-            for (int jj = 0; jj < 64; ++jj) {
-                const int p = grp * 64 + jj;
-                const float px = (float)(tx * S + p % S) + 0.5f;
-                const float py = (float)(ty * S + p / S) + 0.5f;
-                const float4 c0 = s_pc[wave][jj][0];
-                const float Bc = s_pc[wave][jj][1].x;
-                const float dx = px - mx, dy = py - my;
-                const float e = alpha_exponent(lo, qa, qb, qc, dx, dy);
-                if (e >= kLog2AlphaMin) {
-                    const bool capped = e > kLog2AlphaMax;
-                    const float al = capped ? kAlphaMax : exp2f(e);
-                    const float diff = fmaf(c0.x, cr, fmaf(c0.y, cg, c0.z * cb)) - c0.w;
-                    const float aw = al * w;
-                    g_cr = fmaf(c0.x, aw, g_cr);
-                    g_cg = fmaf(c0.y, aw, g_cg);
-                    g_cb = fmaf(c0.z, aw, g_cb);
-                    g_w = fmaf(al, diff, g_w);
-                    if (!capped) {
-                        const float dLda = fmaf(w, diff, Bc / (1.f - al));
-                        const float dLde = dLda * al * kLn2;
-                        g_lo += dLde;
-                        const float ex = dLde * dx, ey = dLde * dy;
-                        g_qa = fmaf(ex, dx, g_qa);
-                        g_qb = fmaf(ex, dy, g_qb);
-                        g_qc = fmaf(ey, dy, g_qc);
-                        // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
-                        g_mx -= fmaf(2.f * qa, ex, qb * ey);
-                        g_my -= fmaf(qb, ex, 2.f * qc * ey);
+            // walk the group row by row; per-row terms of the exponent are hoisted, and
+            // the exponent is formed with the same operations as alpha_exponent() so that
+            // forward and backward take identical decisions for every pair
+            for (int row = 0; row < ROWS; ++row) {
+                const int y = ty * S + grp * ROWS + row;
+                if (y >= cam.H) break;
+                const float dy = ((float)y + 0.5f) - my;
+                const float qbdy = qb * dy;
+                const float cterm = fmaf(qc * dy, dy, lo);
+#pragma unroll
+                for (int col = 0; col < S; ++col) {
+                    if (col >= cols) break;
+                    const float dx = ((float)(tx * S + col) + 0.5f) - mx;
+                    const float e = fmaf(dx, fmaf(qa, dx, qbdy), cterm);
+                    if (e >= kLog2AlphaMin) {
+                        const int jj = row * S + col;
+                        const float4 c0 = s_pc[wave][jj][0];
+                        const bool capped = e > kLog2AlphaMax;
+                        const float al = capped ? kAlphaMax : __builtin_amdgcn_exp2f(e);
+                        const float diff = fmaf(c0.x, cr, fmaf(c0.y, cg, c0.z * cb)) - c0.w;
+                        const float aw = al * w;
+                        g_cr = fmaf(c0.x, aw, g_cr);
+                        g_cg = fmaf(c0.y, aw, g_cg);
+                        g_cb = fmaf(c0.z, aw, g_cb);
+                        g_w = fmaf(al, diff, g_w);
+                        if (!capped) {
+                            const float Bc = s_pc[wave][jj][1].x;
+                            // dL/dalpha = B / (1 - alpha) + w diff;  d alpha / de = alpha ln 2
+                            // (the ln 2 is applied once per work item, below)
+                            const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                            const float dLde = dLda * al;
+                            g_lo += dLde;
+                            const float ex = dLde * dx, ey = dLde * dy;
+                            g_qa = fmaf(ex, dx, g_qa);
+                            g_qb = fmaf(ex, dy, g_qb);
+                            g_qc = fmaf(ey, dy, g_qc);
+                            // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
+                            g_mx -= fmaf(2.f * qa, ex, qb * ey);
+                            g_my -= fmaf(qb, ex, 2.f * qc * ey);
+                        }
                     }
                 }
             }
@@ -256,7 +269,8 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a)
         }
         if (valid) {
             float *dst = a.b.sgrad + ((size_t)v * a.b.Acap + r) * 10;
-            const float vals[10] = {g_mx, g_my, g_qa, g_qb, g_qc, g_lo, g_cr, g_cg, g_cb, g_w};
+            const float vals[10] = {g_mx * kLn2, g_my * kLn2, g_qa * kLn2, g_qb * kLn2, g_qc * kLn2, g_lo * kLn2,
+                                    g_cr, g_cg, g_cb, g_w};
 #pragma unroll
             for (int k = 0; k < 10; ++k)
                 if (vals[k] != 0.f) unsafeAtomicAdd(dst + k, vals[k]);

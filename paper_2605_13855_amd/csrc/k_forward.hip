@@ -379,7 +379,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                 const float dx = px[p] - ra.x, dy = py[p] - ra.y;
                 const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
                 if (e >= kLog2AlphaMin) {
-                    const float al = fminf(exp2f(e), kAlphaMax);
+                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
                     const float aw = al * rc.y;
                     P[p][0] = fmaf(rb.z, aw, P[p][0]);
                     P[p][1] = fmaf(rb.w, aw, P[p][1]);
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                 const float dx = px[p] - ra.x, dy = py[p] - ra.y;
                 const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
                 if (e >= kLog2AlphaMin) {
-                    const float al = fminf(exp2f(e), kAlphaMax);
+                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
                     const float sav = rc.w * al * rc.y;       // sign * alpha * v
                     const float savd = sav * rc.z;            // ... * d
                     dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                     dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
                     dQ0[p] += sav;
                     dQ1[p] += savd;
-                    dL[p] = fmaf(rc.w, logf(1.f - al), dL[p]);
+                    dL[p] = fmaf(rc.w, __builtin_amdgcn_logf(1.f - al) * kLn2, dL[p]);
                 }
             }
         }
