@@ -213,6 +213,30 @@ oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, in
                                  void *ws, size_t ws_bytes, oit_stream stream);
 
 /*
+ * Label changes between two label arrays (for pre-rendered buffers that fell behind
+ * several active-set updates: the paper delays the pre-render update of a view until
+ * the view is next used, Sec. 4.1 "Implementation Details").
+ * old_label, new_label [n] uint8 (1 = active), unchanged.
+ * active_idx [active_capacity], n_active: the rows of new_label, ascending (both may be
+ * NULL); delta_idx, delta_sign, n_delta: the rows whose label differs, ascending, with
+ * sign -1 (active in new_label: leaves pre) or +1 (inactive in new_label: joins pre).
+ * Workspace as for oit_update_active_set.
+ */
+oit_status oit_label_delta(const uint8_t *old_label, const uint8_t *new_label, int64_t n,
+                           int32_t *active_idx, int64_t active_capacity, int32_t *n_active,
+                           int32_t *delta_idx, int8_t *delta_sign, int64_t delta_capacity,
+                           int32_t *n_delta, void *ws, size_t ws_bytes, oit_stream stream);
+
+/*
+ * Farthest-point sampling of s views from n camera centres (host; Sec. 4.1: the active
+ * set is updated from a subset of training views picked by farthest point sampling
+ * with a random initialisation; the caller draws `start`).  centres (host) [n][3];
+ * out (host) [s] in pick order: start, then repeatedly the view whose squared distance
+ * to the nearest picked view is largest (ties to the lower index), in double precision.
+ */
+oit_status oit_fps_views(const float *centres, int32_t n, int32_t s, int32_t start, int32_t *out);
+
+/*
  * Adam on the active rows only (Sec. 4.1, Alg. "Active Set Method": the update
  * touches only the active splats; the optimiser is Adam, Sec. 5.1).
  * For every active row i (splat id active_idx[r], compact gradient row r) and

@@ -287,3 +287,18 @@ def adam_rows(param, grad_rows, m, v, rows, lr, beta1, beta2, eps, step):
     mhat = m[:, rows] / (1.0 - beta1 ** step)
     vhat = v[:, rows] / (1.0 - beta2 ** step)
     param[:, rows] = param[:, rows] - lr * mhat / (np.sqrt(vhat) + eps)
+
+
+def fps(centres, s, start):
+    """Farthest-point sampling over camera centres (Sec. 4.1: the active set is updated
+    on a subset of training views chosen by farthest point sampling from a random
+    start).  Picks ``start``, then repeatedly the point whose squared distance to the
+    nearest picked point is largest (first such index on ties)."""
+    c = np.asarray(centres, dtype=np.float32).astype(np.float64)
+    picked = [int(start)]
+    d = ((c - c[start]) ** 2).sum(axis=1)
+    for _ in range(int(s) - 1):
+        j = int(np.argmax(d))
+        picked.append(j)
+        d = np.minimum(d, ((c - c[j]) ** 2).sum(axis=1))
+    return picked

@@ -56,6 +56,8 @@ struct SelArgs {
     int64_t dcap;
     int32_t *n_delta;
     SelectBuffers sb;
+    const uint8_t *new_label;   // label-diff mode: the target labels
+    bool write_label;           // store the new labels into `label`
 };
 
 __global__ void k_sel_init(SelArgs a, uint32_t prefix, uint32_t krem, uint32_t mask)
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_write(SelArgs a)
         if (i >= a.n) break;
         const bool sel = f[k] & 1, chg = (f[k] >> 1) & 1;
         if (sel) {
-            if ((int64_t)ps < a.acap) a.active_idx[ps] = (int32_t)i;
+            if (a.active_idx && (int64_t)ps < a.acap) a.active_idx[ps] = (int32_t)i;
             ++ps;
         }
         if (chg) {
@@ -243,15 +245,50 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_write(SelArgs a)
             }
             ++pd;
         }
-        a.label[i] = sel ? 1 : 0;
+        if (a.write_label) a.label[i] = sel ? 1 : 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t tsel = a.sb.blk_b[a.sb.nblk], tdel = a.sb.blk_c[a.sb.nblk];
-        *a.n_active = (int32_t)((int64_t)tsel < a.acap ? tsel : a.acap);
+        if (a.n_active) *a.n_active = (int32_t)((int64_t)tsel < a.acap ? tsel : a.acap);
         *a.n_delta = (int32_t)((int64_t)tdel < a.dcap ? tdel : a.dcap);
-        if ((int64_t)tsel > a.acap) atomicOr(a.sb.status, OIT_STATUS_ACTIVE_OVERFLOW);
+        if (a.active_idx && (int64_t)tsel > a.acap) atomicOr(a.sb.status, OIT_STATUS_ACTIVE_OVERFLOW);
         if ((int64_t)tdel > a.dcap) atomicOr(a.sb.status, OIT_STATUS_DELTA_OVERFLOW);
     }
+}
+
+// label-diff mode: flags and per-block counts from two label arrays
+__global__ __launch_bounds__(kSelThreads) void k_lab_flags(SelArgs a)
+{
+    const int64_t base = (int64_t)blockIdx.x * kSelBlock + (int64_t)threadIdx.x * kSelPerThread;
+    uint32_t csel = 0, cdel = 0;
+    for (int k = 0; k < kSelPerThread; ++k) {
+        const int64_t i = base + k;
+        if (i >= a.n) break;
+        const bool sel = a.new_label[i] != 0;
+        const bool chg = (a.label[i] != 0) != sel;
+        a.sb.flags[i] = (uint8_t)((sel ? 1 : 0) | (chg ? 2 : 0));
+        csel += sel;
+        cdel += chg;
+    }
+    uint32_t ts, td;
+    block_excl_scan(csel, &ts);
+    block_excl_scan(cdel, &td);
+    if (threadIdx.x == 0) {
+        a.sb.blk_b[blockIdx.x] = ts;
+        a.sb.blk_c[blockIdx.x] = td;
+    }
+}
+
+void launch_label_delta(const uint8_t *old_label, const uint8_t *new_label, int64_t n, int32_t *active_idx,
+                        int64_t acap, int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign, int64_t dcap,
+                        int32_t *n_delta, const SelectBuffers &sb, hipStream_t s)
+{
+    SelArgs a{nullptr, n, const_cast<uint8_t *>(old_label), active_idx, acap, n_active, delta_idx, delta_sign,
+              dcap, n_delta, sb, new_label, false};
+    const unsigned nblk = (unsigned)sb.nblk;
+    hipLaunchKernelGGL(k_lab_flags, dim3(nblk), dim3(kSelThreads), 0, s, a);
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, s, sb.blk_b, sb.blk_c, sb.nblk);
+    hipLaunchKernelGGL(k_sel_write, dim3(nblk), dim3(kSelThreads), 0, s, a);
 }
 
 static uint32_t host_order_key(float f)
@@ -266,7 +303,7 @@ void launch_select(const float *score, int64_t n, int mode, int64_t k, float thr
                    int8_t *delta_sign, int64_t dcap, int32_t *n_delta, const SelectBuffers &sb,
                    hipStream_t s)
 {
-    SelArgs a{score, n, label, active_idx, acap, n_active, delta_idx, delta_sign, dcap, n_delta, sb};
+    SelArgs a{score, n, label, active_idx, acap, n_active, delta_idx, delta_sign, dcap, n_delta, sb, nullptr, true};
     const unsigned nblk = (unsigned)sb.nblk;
     bool radix = false;
     if (mode == OIT_SELECT_THRESHOLD) {

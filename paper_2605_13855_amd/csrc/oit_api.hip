@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "oit_internal.h"
 
@@ -232,6 +233,12 @@ SplatPtrs splat_ptrs(const oit_splats *s)
     return SplatPtrs{s->mean, s->log_scale, s->quat, s->opacity_logit, s->sh, s->vsh, s->n};
 }
 
+SelectBuffers select_buffers(void *ws, int64_t n)
+{
+    const SelectBuffers sb = select_buffers(ws, n);
+    return sb;
+}
+
 }  // namespace
 
 extern "C" {
@@ -375,22 +382,57 @@ oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, in
     const size_t need = oit_select_workspace_bytes(n);
     if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    const int64_t nblk = (n + 1023) / 1024;
-    char *w = (char *)ws;
-    size_t o = 0;
-    SelectBuffers sb;
-    sb.status = (int32_t *)(w + o); o = align256(o + 4);
-    sb.state = (uint32_t *)(w + o); o = align256(o + 4 * 8);
-    sb.hist = (uint32_t *)(w + o); o = align256(o + 4 * 2048);
-    sb.blk_a = (uint32_t *)(w + o);
-    sb.blk_b = sb.blk_a + (nblk + 1);
-    sb.blk_c = sb.blk_b + (nblk + 1);
-    o = align256(o + 4 * 3 * (size_t)(nblk + 1));
-    sb.flags = (uint8_t *)(w + o);
-    sb.nblk = nblk;
+    const SelectBuffers sb = select_buffers(ws, n);
     launch_select(score, n, mode, k, thresh, label, active_idx, active_capacity, n_active, delta_idx, delta_sign,
                   delta_capacity, n_delta, sb, (hipStream_t)stream);
     return check_launch("oit_update_active_set");
+}
+
+
+oit_status oit_label_delta(const uint8_t *old_label, const uint8_t *new_label, int64_t n, int32_t *active_idx,
+                           int64_t active_capacity, int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign,
+                           int64_t delta_capacity, int32_t *n_delta, void *ws, size_t ws_bytes, oit_stream stream)
+{
+    if (n <= 0 || n > 0x7fffffffLL) return fail(OIT_ERR_INVALID, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!old_label || !new_label || !delta_idx || !delta_sign || !n_delta)
+        return fail(OIT_ERR_INVALID, "oit_label_delta: NULL buffer");
+    if ((active_idx == nullptr) != (n_active == nullptr))
+        return fail(OIT_ERR_INVALID, "active_idx and n_active go together");
+    if (delta_capacity <= 0 || (active_idx && active_capacity <= 0))
+        return fail(OIT_ERR_INVALID, "capacities must be positive");
+    const size_t need = oit_select_workspace_bytes(n);
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    launch_label_delta(old_label, new_label, n, active_idx, active_capacity, n_active, delta_idx, delta_sign,
+                       delta_capacity, n_delta, select_buffers(ws, n), (hipStream_t)stream);
+    return check_launch("oit_label_delta");
+}
+
+oit_status oit_fps_views(const float *centres, int32_t n, int32_t s, int32_t start, int32_t *out)
+{
+    if (!centres || !out) return fail(OIT_ERR_INVALID, "oit_fps_views: NULL argument");
+    if (n <= 0 || s <= 0 || s > n) return fail(OIT_ERR_INVALID, "oit_fps_views: need 0 < s <= n");
+    if (start < 0 || start >= n) return fail(OIT_ERR_INVALID, "oit_fps_views: start outside [0, n)");
+    std::vector<double> d(n);
+    auto dist2 = [&](int i, int j) {
+        const double dx = (double)centres[3 * i] - (double)centres[3 * j];
+        const double dy = (double)centres[3 * i + 1] - (double)centres[3 * j + 1];
+        const double dz = (double)centres[3 * i + 2] - (double)centres[3 * j + 2];
+        return dx * dx + dy * dy + dz * dz;
+    };
+    out[0] = start;
+    for (int i = 0; i < n; ++i) d[i] = dist2(i, start);
+    for (int k = 1; k < s; ++k) {
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (d[i] > d[best]) best = i;
+        out[k] = best;
+        for (int i = 0; i < n; ++i) {
+            const double e = dist2(i, best);
+            if (e < d[i]) d[i] = e;
+        }
+    }
+    return ok();
 }
 
 oit_status oit_sparse_adam_step(float *const *params, const oit_grads *grads, float *const *m, float *const *v,

@@ -98,6 +98,10 @@ void launch_select(const float *score, int64_t n, int mode, int64_t k, float thr
                    int8_t *delta_sign, int64_t dcap, int32_t *n_delta, const SelectBuffers &sb,
                    hipStream_t s);
 
+void launch_label_delta(const uint8_t *old_label, const uint8_t *new_label, int64_t n, int32_t *active_idx,
+                        int64_t acap, int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign, int64_t dcap,
+                        int32_t *n_delta, const SelectBuffers &sb, hipStream_t s);
+
 struct AdamPtrs {
     float *p[6];
     const float *g[6];

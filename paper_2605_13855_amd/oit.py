@@ -73,13 +73,16 @@ def _load():
     L.oit_read_status.argtypes = [P, SZ, P, P]
     L.oit_clear_status.argtypes = [P, SZ, P]
     L.oit_read_counters.argtypes = [P, SZ, P, P, I32, P, P, P]
+    L.oit_label_delta.argtypes = [P, P, I64, P, I64, P, P, P, I64, P, P, SZ, P]
+    L.oit_fps_views.argtypes = [P, I32, I32, I32, P]
     L.oit_timing_enable.argtypes = [I32]
     L.oit_timing_read.argtypes = [P]
     L.oit_last_error.argtypes = []
     L.oit_last_error.restype = ctypes.c_char_p
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
-              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read):
+              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_label_delta,
+              L.oit_fps_views):
         f.restype = ctypes.c_int
     return L
 
@@ -182,6 +185,24 @@ def update_active_set(score, n, mode, k, thresh, label, active_idx, n_active, de
                                    _ptr(delta_sign), delta_idx.numel(), _ptr(n_delta), _ptr(ws), ws.numel(),
                                    _stream(stream))
     _check(rc, "oit_update_active_set")
+
+
+def label_delta(old_label, new_label, n, active_idx, n_active, delta_idx, delta_sign, n_delta, ws, stream=None):
+    rc = lib.oit_label_delta(_ptr(old_label), _ptr(new_label), int(n), _ptr(active_idx),
+                             active_idx.numel() if active_idx is not None else 0, _ptr(n_active), _ptr(delta_idx),
+                             delta_sign.data_ptr() if delta_sign is not None else None, delta_idx.numel(),
+                             _ptr(n_delta), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "oit_label_delta")
+
+
+def fps_views(centres, s: int, start: int):
+    """centres: host float array [n][3]; returns the s picked view indices."""
+    import numpy as np
+    c = np.ascontiguousarray(centres, dtype=np.float32)
+    out = (ctypes.c_int32 * int(s))()
+    rc = lib.oit_fps_views(ctypes.c_void_p(c.ctypes.data), int(c.shape[0]), int(s), int(start), out)
+    _check(rc, "oit_fps_views")
+    return [int(x) for x in out]
 
 
 def sparse_adam_step(params: dict, grads: Grads, m: dict, v: dict, active_idx, n_active, n, lr, beta1, beta2,

@@ -66,8 +66,10 @@ class Renderer:
         self.tuning = oit.Tuning(int(tile), int(batch), int(pair_capacity))
         self._alloc_ws()
         dev = self.device
-        self.image = torch.zeros(3 * self.total_px, device=dev)
-        self.pixstate = torch.zeros(5 * self.total_px, device=dev)
+        self._image_buf = torch.zeros(3 * self.total_px, device=dev)
+        self._pixstate_buf = torch.zeros(5 * self.total_px, device=dev)
+        self.image = self._image_buf
+        self.pixstate = self._pixstate_buf
 
     def _alloc_ws(self):
         nb = oit.workspace_bytes(self.cap, self.cams_arr, self.n_views, self.tuning)
@@ -75,6 +77,25 @@ class Renderer:
             raise oit.OITError(oit.lib.oit_last_error().decode())
         self.ws = _aligned_workspace(nb, self.device)
         oit.clear_status(self.ws)
+
+    def use_cameras(self, cams):
+        """Point the renderer at another batch of views; the workspace and the per-pixel
+        buffers grow only when the new batch needs more."""
+        self.cams = list(cams)
+        self.n_views = len(self.cams)
+        self.cams_arr = oit.camera_array(self.cams)
+        self.hw = [c.height * c.width for c in self.cams]
+        self.total_px = sum(self.hw)
+        nb = oit.workspace_bytes(self.cap, self.cams_arr, self.n_views, self.tuning)
+        if nb == 0:
+            raise oit.OITError(oit.lib.oit_last_error().decode())
+        if nb > self.ws.numel():
+            self._alloc_ws()
+        if 5 * self.total_px > self._pixstate_buf.numel():
+            self._image_buf = torch.zeros(3 * self.total_px, device=self.device)
+            self._pixstate_buf = torch.zeros(5 * self.total_px, device=self.device)
+        self.image = self._image_buf[:3 * self.total_px]
+        self.pixstate = self._pixstate_buf[:5 * self.total_px]
 
     def set_tuning(self, tile=None, batch=None, pair_capacity=None):
         self.tuning = oit.Tuning(int(tile or self.tuning.tile), int(batch or self.tuning.batch),

@@ -524,3 +524,20 @@ def test_adam_rows_matches_torch_adam():
     keep = [i for i in range(9) if i not in (2, 7)]
     assert np.array_equal(q[:, keep], p[:, keep])
     assert np.array_equal(mm[:, keep], m[:, keep])
+
+
+def test_fps_spreads_views_and_matches_brute_force():
+    """FPS: each pick maximises the distance to the picked set (checked by brute force);
+    on a ring of equally spaced points the first two picks are antipodal."""
+    rng = np.random.default_rng(18)
+    c = rng.normal(size=(40, 3)).astype(np.float32)
+    got = O.fps(c, 10, 7)
+    assert got[0] == 7 and len(set(got)) == 10
+    cd = c.astype(np.float64)
+    for k in range(1, 10):
+        picked = got[:k]
+        dist = np.array([min(((cd[i] - cd[j]) ** 2).sum() for j in picked) for i in range(40)])
+        assert dist[got[k]] == dist.max()
+    ang = np.arange(12) * (2 * math.pi / 12)
+    ring = np.stack([np.cos(ang), np.sin(ang), np.zeros(12)], axis=1)
+    assert O.fps(ring, 2, 0) == [0, 6]
