@@ -756,11 +756,12 @@ int orc_backward(const orc_splats *s, double sigma, const double bg[3], const or
 
 /*
  * Same gradient with dLdC given only at a list of pixels (zero elsewhere):
- * pixel-major over all splats.  dLdC [npix][3].
+ * pixel-major over all splats.  dLdC [npix][3]; screen [n][10] optional, as in
+ * orc_backward.
  */
 int orc_backward_pixels(const orc_splats *s, double sigma, const double bg[3], const orc_camera *cam,
                         long npix, const int *pxs, const int *pys, const double *dLdC,
-                        orc_grads *gr, double *g_sigma)
+                        orc_grads *gr, double *g_sigma, double *screen)
 {
     const long n = s->n;
     orc_proj *pr = (orc_proj *)malloc(sizeof(orc_proj) * (n > 0 ? n : 1));
@@ -792,8 +793,15 @@ int orc_backward_pixels(const orc_splats *s, double sigma, const double bg[3], c
         }
     }
     double gsig = 0.0;
-    for (long i = 0; i < n; ++i)
+    for (long i = 0; i < n; ++i) {
         if (pr[i].valid) splat_backward(s, i, sigma, cam, &pr[i], &sg[i], gr, &gsig);
+        if (screen) {
+            double *o = screen + 10 * i;
+            o[0] = sg[i].mx; o[1] = sg[i].my; o[2] = sg[i].conic[0]; o[3] = sg[i].conic[1] + sg[i].conic[2];
+            o[4] = sg[i].conic[3]; o[5] = sg[i].opacity;
+            o[6] = sg[i].color[0]; o[7] = sg[i].color[1]; o[8] = sg[i].color[2]; o[9] = sg[i].w;
+        }
+    }
     *g_sigma += gsig;
     free(pr);
     free(sg);

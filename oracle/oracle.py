@@ -74,7 +74,7 @@ def lib():
                                  ctypes.c_double, P, P]
         L.orc_render_pixels.argtypes = [P, ctypes.c_double, P, P, ctypes.c_long, P, P, P, P, P]
         L.orc_backward.argtypes = [P, ctypes.c_double, P, P, P, P, P, P, P]
-        L.orc_backward_pixels.argtypes = [P, ctypes.c_double, P, P, ctypes.c_long, P, P, P, P, P]
+        L.orc_backward_pixels.argtypes = [P, ctypes.c_double, P, P, ctypes.c_long, P, P, P, P, P, P]
         L.orc_sh_basis.argtypes = [P, P, P]
         L.orc_quat_to_rot.argtypes = [P, P]
         for f in (L.orc_project, L.orc_render, L.orc_render_pixels, L.orc_backward,
@@ -208,9 +208,11 @@ def backward(params, sigma, bg, cam, dLdC, window=None, screen=False):
     return grads, gs.value, scr
 
 
-def backward_pixels(params, sigma, bg, cam, xs, ys, dLdC):
-    """Gradient of sum_k dLdC[k] . C(pixel k) for a pixel list (dLdC [npix][3])."""
+def backward_pixels(params, sigma, bg, cam, xs, ys, dLdC, screen=False):
+    """Gradient of sum_k dLdC[k] . C(pixel k) for a pixel list (dLdC [npix][3]).
+    Returns (grads, d/dsigma) or, with ``screen``, (grads, d/dsigma, screen [n][10])."""
     pk = _Pack(params)
+    scr = np.zeros((pk.n, 10)) if screen else None
     grads = _zero_grads(pk.n)
     gr = _Grads(*[grads[g].ctypes.data for g, _ in GROUPS])
     gs = ctypes.c_double(0.0)
@@ -221,8 +223,10 @@ def backward_pixels(params, sigma, bg, cam, xs, ys, dLdC):
     bgd = np.ascontiguousarray(bg, np.float64)
     rc = lib().orc_backward_pixels(ctypes.byref(pk.s), float(sigma), _ptr(bgd), ctypes.byref(c),
                                    len(xs), _ptr(xs), _ptr(ys), _ptr(g), ctypes.byref(gr),
-                                   ctypes.byref(gs))
+                                   ctypes.byref(gs), _ptr(scr))
     assert rc == 0
+    if screen:
+        return grads, gs.value, scr
     return grads, gs.value
 
 

@@ -233,9 +233,25 @@ SplatPtrs splat_ptrs(const oit_splats *s)
     return SplatPtrs{s->mean, s->log_scale, s->quat, s->opacity_logit, s->sh, s->vsh, s->n};
 }
 
+// Layout of the selection workspace; sizes as in oit_select_workspace_bytes.
 SelectBuffers select_buffers(void *ws, int64_t n)
 {
-    const SelectBuffers sb = select_buffers(ws, n);
+    const int64_t nblk = (n + 1023) / 1024;
+    char *w = (char *)ws;
+    size_t o = 0;
+    SelectBuffers sb;
+    sb.status = (int32_t *)(w + o);
+    o = align256(o + 4);
+    sb.state = (uint32_t *)(w + o);
+    o = align256(o + 4 * 8);
+    sb.hist = (uint32_t *)(w + o);
+    o = align256(o + 4 * 2048);
+    sb.blk_a = (uint32_t *)(w + o);
+    sb.blk_b = sb.blk_a + (nblk + 1);
+    sb.blk_c = sb.blk_b + (nblk + 1);
+    o = align256(o + 4 * 3 * (size_t)(nblk + 1));
+    sb.flags = (uint8_t *)(w + o);
+    sb.nblk = nblk;
     return sb;
 }
 
@@ -277,10 +293,10 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     launch_preprocess_count(splat_ptrs(splats), sigma, rl, b, s);
     launch_scan_tiles(b, s);
     launch_emit(rl, b, s);
-    if (g_timing_on) hipEventRecord(g_ev[0], s);
+    if (g_timing_on) (void)hipEventRecord(g_ev[0], s);
     if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
-    if (g_timing_on) hipEventRecord(g_ev[1], s);
+    if (g_timing_on) (void)hipEventRecord(g_ev[1], s);
     return check_launch("oit_render_fwd");
 }
 
@@ -345,9 +361,9 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     fill_u32(b.counters + CNT_BWD_WORK, 1, 0u, s);
     fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
-    if (g_timing_on) hipEventRecord(g_ev[2], s);
+    if (g_timing_on) (void)hipEventRecord(g_ev[2], s);
     if (!launch_raster_bwd(b, rl, s)) return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
-    if (g_timing_on) hipEventRecord(g_ev[3], s);
+    if (g_timing_on) (void)hipEventRecord(g_ev[3], s);
     launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
     return check_launch("oit_render_bwd");
 }

@@ -67,3 +67,18 @@ def test_workspace_grows_with_views_and_capacity(lib):
     b = oit.workspace_bytes(oit.Capacity(100, 100, 0), cams2, 2, tu)
     c = oit.workspace_bytes(oit.Capacity(100, 50, 50), cams1, 1, tu)
     assert b > a and c < a + 100 * 100
+
+
+def test_host_api_compiles_without_warnings():
+    """The host layer compiles warning-free with -Wall (an infinitely recursive helper, for
+    one, is only visible as a warning and once sent garbage pointers to the GPU)."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2605_13855_amd import build as B
+    src = os.path.join(ROOT, "paper_2605_13855_amd", "csrc", "oit_api.hip")
+    cmd = [B.hipcc(), *B.FLAGS, "-c", src, "-o", os.devnull]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    bad = [ln for ln in (r.stdout + r.stderr).splitlines() if "warning:" in ln and not B._benign(ln)]
+    assert not bad, bad

@@ -104,11 +104,15 @@ def run_case(sc, n_px, seed, active_fraction=None, tile=16):
     gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
     r.backward(params, sigma, sc.background, gimg, g_gpu, gsig, act, pre)
     torch.cuda.synchronize()
-    tot, s_ref = None, 0.0
+    tot, s_ref, s_abs = None, 0.0, 0.0
+    F = {f: k for k, f in enumerate(O.PROJECT_FIELDS)}
     for v, cam in enumerate(sc.cameras):
         xs, ys, g = samples[v]
-        gr, s = O.backward_pixels(sc.params, sc.sigma, sc.background, cam, xs, ys, g)
+        gr, s, scr = O.backward_pixels(sc.params, sc.sigma, sc.background, cam, xs, ys, g, screen=True)
         s_ref += s
+        pr = O.project(sc.params, sc.sigma, cam)
+        on = (pr[:, F["valid"]] > 0) & (pr[:, F["d"]] < sc.sigma)
+        s_abs += float(np.abs(scr[:, 9] * pr[:, F["v"]] * pr[:, F["d"]] / sc.sigma ** 2)[on].sum())
         tot = gr if tot is None else {k: tot[k] + gr[k] for k in tot}
     sel = np.arange(n) if act is None else act["idx"][:rows].cpu().numpy()
     ref = {k: v[:, sel] for k, v in tot.items()}
@@ -117,8 +121,10 @@ def run_case(sc, n_px, seed, active_fraction=None, tile=16):
         rel, den = grad_rel(to_np(g_gpu[name])[:, :rows], ref[name], fl)
         log(f"  grad {name}: rel {rel:.2e} (norm {den:.3e})")
         assert rel <= GRAD_RTOL
-    srel = abs(float(gsig.item()) - s_ref) / max(abs(s_ref), 1e-30)
-    log(f"  grad sigma: rel {srel:.2e}")
+    # dL/dsigma sums signed terms that largely cancel on a sparse pixel sample: its error is
+    # measured against max(|dL/dsigma|, 1e-3 sum |terms|), as in the dense tests
+    srel = abs(float(gsig.item()) - s_ref) / max(abs(s_ref), 1e-3 * s_abs, 1e-30)
+    log(f"  grad sigma: gpu {float(gsig.item()):.6e} oracle {s_ref:.6e} (sum |terms| {s_abs:.3e}) rel {srel:.2e}")
     assert srel <= SIGMA_RTOL
 
 
