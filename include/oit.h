@@ -133,6 +133,11 @@ size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int3
  *             for a splat that joined the active set (its share leaves pre) and +1 for
  *             one that left it (its share joins pre); n_delta [1] device int32.
  *             All three NULL when no label changed.
+ * delta_splats parameters the label-change rows are added to / removed from pre with;
+ *             NULL = `splats`.  A pre buffer that is brought up to date lazily (some
+ *             updates after the labels changed) must remove a splat with the values it
+ *             was added with, although the splat may have been trained since it became
+ *             active: pass the parameters as they were when the labels changed.
  * pre         [V][9][H][W] per-pixel accumulators of the inactive set: P0 (rgb),
  *             P1 (rgb), Q0, Q1, logT with P0 = sum c alpha v, P1 = sum c alpha v d,
  *             Q0 = sum alpha v, Q1 = sum alpha v d over inactive splats with d < sigma,
@@ -146,6 +151,7 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
                           const oit_camera *cams, int32_t n_views, const oit_capacity *cap,
                           const int32_t *active_idx, const int32_t *n_active,
                           const int32_t *delta_idx, const int8_t *delta_sign, const int32_t *n_delta,
+                          const oit_splats *delta_splats,
                           float *pre, float *image, float *pixstate,
                           void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream);
 

@@ -88,7 +88,8 @@ __device__ __forceinline__ bool tile_hit(const Rec &r, float tau, const CamDev &
 // rectangles and counts the tile entries.
 // ---------------------------------------------------------------------------------
 struct PreArgs {
-    SplatPtrs sp;
+    SplatPtrs sp;    // active rows
+    SplatPtrs dsp;   // label-change rows
     const float *sigma;
     RowList rl;
     Buffers b;
@@ -101,28 +102,29 @@ __global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
     int sign = 0;
     const int64_t id = record_row(a.rl, t, sign);
     if (id < 0) return;
-    const int64_t n = a.sp.n;
+    const SplatPtrs &sp = sign == 0 ? a.sp : a.dsp;
+    const int64_t n = sp.n;
     const float sigma = *a.sigma;
 
     float mu[3], s[3], q[4];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        mu[k] = a.sp.mean[k * n + id];
-        s[k] = expf(a.sp.log_scale[k * n + id]);
+        mu[k] = sp.mean[k * n + id];
+        s[k] = expf(sp.log_scale[k * n + id]);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[k * n + id];
+    for (int k = 0; k < 4; ++k) q[k] = sp.quat[k * n + id];
     const float qi = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     float Rq[9], S6[6];
     quat_rot(q[0] * qi, q[1] * qi, q[2] * qi, q[3] * qi, Rq);
     cov3d(Rq, s, S6);
-    const float lg = a.sp.logit[id];
+    const float lg = sp.logit[id];
     const float lo = -log2f(1.f + expf(-lg));   // log2(sigmoid(logit))
     float shc[48], vsc[16];
 #pragma unroll
-    for (int k = 0; k < 48; ++k) shc[k] = a.sp.sh[k * n + id];
+    for (int k = 0; k < 48; ++k) shc[k] = sp.sh[k * n + id];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) vsc[k] = a.sp.vsh[k * n + id];
+    for (int k = 0; k < 16; ++k) vsc[k] = sp.vsh[k * n + id];
 
     const int S = a.b.tile;
     for (int v = 0; v < a.b.n_views; ++v) {
@@ -196,10 +198,10 @@ __global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
     }
 }
 
-void launch_preprocess_count(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
-                             hipStream_t s)
+void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const float *sigma, const RowList &rl,
+                             const Buffers &b, hipStream_t s)
 {
-    PreArgs a{sp, sigma, rl, b};
+    PreArgs a{sp, dsp, sigma, rl, b};
     const unsigned blocks = (unsigned)((rl.Rcap + 255) / 256);
     if (blocks) hipLaunchKernelGGL(k_preprocess_count, dim3(blocks), dim3(256), 0, s, a);
 }

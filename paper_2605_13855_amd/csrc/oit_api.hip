@@ -270,13 +270,14 @@ size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int3
 oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const float *bg, const oit_camera *cams,
                           int32_t n_views, const oit_capacity *cap, const int32_t *active_idx,
                           const int32_t *n_active, const int32_t *delta_idx, const int8_t *delta_sign,
-                          const int32_t *n_delta, float *pre, float *image, float *pixstate, void *ws,
-                          size_t ws_bytes, const oit_tuning *tuning, oit_stream stream)
+                          const int32_t *n_delta, const oit_splats *delta_splats, float *pre, float *image,
+                          float *pixstate, void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream)
 {
     Plan p;
     oit_status st;
     if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
     if ((st = check_splats(splats, cap)) != OIT_OK) return st;
+    if (delta_splats && (st = check_splats(delta_splats, cap)) != OIT_OK) return st;
     if ((st = check_rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, pre)) != OIT_OK) return st;
     if (!sigma || !bg || !image || !pixstate) return fail(OIT_ERR_INVALID, "sigma, bg, image and pixstate are required");
     if (!aligned(image, 4) || !aligned(pixstate, 4) || (pre && !aligned(pre, 4)))
@@ -290,7 +291,7 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.cnt_a, 4 * (size_t)p.T, 0u, s);
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
-    launch_preprocess_count(splat_ptrs(splats), sigma, rl, b, s);
+    launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
     launch_scan_tiles(b, s);
     launch_emit(rl, b, s);
     if (g_timing_on) (void)hipEventRecord(g_ev[0], s);

@@ -69,8 +69,8 @@ void fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 void fill_f32(float *p, size_t n, float v, hipStream_t s);
 void fill_f64(double *p, size_t n, double v, hipStream_t s);
 
-void launch_preprocess_count(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
-                             hipStream_t s);
+void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const float *sigma, const RowList &rl,
+                             const Buffers &b, hipStream_t s);
 void launch_scan_tiles(const Buffers &b, hipStream_t s);
 void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s);
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,

@@ -62,7 +62,7 @@ def _load():
     P, I32, I64, F, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
     L.oit_workspace_bytes.argtypes = [P, P, I32, P]
     L.oit_workspace_bytes.restype = SZ
-    L.oit_render_fwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.oit_render_fwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.oit_l1_loss.argtypes = [P, P, P, I32, P, P, P, SZ, P]
     L.oit_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.oit_select_workspace_bytes.argtypes = [I64]
@@ -147,10 +147,12 @@ def workspace_bytes(cap: Capacity, cams_arr, n_views: int, tuning: Tuning) -> in
 
 
 def render_fwd(splats: Splats, sigma, bg_host, cams_arr, n_views, cap: Capacity, active_idx, n_active,
-               delta_idx, delta_sign, n_delta, pre, image, pixstate, ws, tuning: Tuning, stream=None):
+               delta_idx, delta_sign, n_delta, pre, image, pixstate, ws, tuning: Tuning, stream=None,
+               delta_splats: Splats = None):
     bg = (ctypes.c_float * 3)(*[float(x) for x in bg_host])
     rc = lib.oit_render_fwd(ctypes.byref(splats), _ptr(sigma), bg, cams_arr, n_views, ctypes.byref(cap),
                             _ptr(active_idx), _ptr(n_active), _ptr(delta_idx), _ptr(delta_sign), _ptr(n_delta),
+                            ctypes.byref(delta_splats) if delta_splats is not None else None,
                             _ptr(pre), _ptr(image), _ptr(pixstate), _ptr(ws), ws.numel(),
                             ctypes.byref(tuning), _stream(stream))
     _check(rc, "oit_render_fwd")

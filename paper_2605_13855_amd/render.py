@@ -115,12 +115,13 @@ class Renderer:
         return torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1) for x in per_view]).to(
             self.device).contiguous()
 
-    def forward(self, params, sigma, bg, active=None, pre=None):
+    def forward(self, params, sigma, bg, active=None, pre=None, delta_params=None):
         sp = oit.splats_struct(params)
+        dsp = oit.splats_struct(delta_params) if delta_params is not None else None
         a = active or {}
         oit.render_fwd(sp, sigma, bg, self.cams_arr, self.n_views, self.cap, a.get("idx"), a.get("n"),
                        a.get("delta_idx"), a.get("delta_sign"), a.get("n_delta"), pre, self.image,
-                       self.pixstate, self.ws, self.tuning)
+                       self.pixstate, self.ws, self.tuning, delta_splats=dsp)
         return self.image
 
     def backward(self, params, sigma, bg, grad_image, grads, grad_sigma, active=None, pre=None, score=None,
@@ -141,10 +142,10 @@ class Renderer:
     def pairs_needed(self) -> int:
         return self.counters()[0]
 
-    def fit_pair_capacity(self, params, sigma, bg, active=None, pre=None, slack=1.25):
+    def fit_pair_capacity(self, params, sigma, bg, active=None, pre=None, slack=1.25, delta_params=None):
         """Run the forward once; grow the pair capacity if the tile lists overflowed."""
         pre_copy = pre.clone() if pre is not None else None
-        self.forward(params, sigma, bg, active, pre_copy)
+        self.forward(params, sigma, bg, active, pre_copy, delta_params)
         st = self.status()
         need = self.pairs_needed()
         if st & oit.STATUS_PAIR_OVERFLOW or need > self.tuning.pair_capacity:

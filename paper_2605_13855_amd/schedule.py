@@ -11,9 +11,11 @@
 * Pre-rendered buffers are brought up to date lazily, when their view is next used
   (Sec. 4.1 "Implementation Details"): a buffer one update behind receives the label
   changes between its labels and the current ones in the same pass that renders it.
-  That is exact because a splat inactive in the buffer's labels was frozen while the
-  buffer waited.  A buffer two or more updates behind could hold a splat that was
-  trained in between, so it is rebuilt from empty (all labels changing from "active").
+  The label-change splats are added and removed with their parameters as of the update
+  (a snapshot taken then): a splat that became active may already have been trained
+  by other views' iterations, but the buffer still holds its frozen contribution.
+  A buffer two or more updates behind could hold a splat that was active and trained
+  in between, so it is rebuilt from empty (all labels changing from "active").
   With ``interval`` >= 2 x views, as the paper chooses, rebuilds never happen.
 """
 from __future__ import annotations
@@ -49,6 +51,7 @@ class PaperScheduleTrainer:
         n = self.n
         self.sigma = torch.tensor([scene.sigma], dtype=torch.float32, device=dev)
         self.m = {g: torch.zeros_like(t) for g, t in self.params.items()}
+        self.snapshot = {g: t.clone() for g, t in self.params.items()}   # parameters at the last update
         self.v = {g: torch.zeros_like(t) for g, t in self.params.items()}
         self.step = torch.zeros(1, dtype=torch.int32, device=dev)
         self.sig_m = torch.zeros(1, device=dev)
@@ -108,6 +111,10 @@ class PaperScheduleTrainer:
                               self.n_active, self.delta_idx, self.delta_sign, self.n_delta, self.sel_ws)
         self.epoch += 1
         self.labels[self.epoch] = new_label
+        # every splat whose label differs between two consecutive epochs is frozen at this
+        # moment: these are the values it was (or will be) added to a pre buffer with
+        for g, p in self.params.items():
+            self.snapshot[g].copy_(p)
         self._forget_labels()
 
     def _forget_labels(self):
@@ -141,8 +148,9 @@ class PaperScheduleTrainer:
         act = self.prepare_view(v)
         self.r.use_cameras([self.cams[v]])
         if fit:
-            self._fit(self.r, act, self.pre[v])
-        self.r.forward(self.params, self.sigma, self.bg, act, self.pre[v])
+            self.r.fit_pair_capacity(self.params, self.sigma, self.bg, act, self.pre[v],
+                                     delta_params=self.snapshot)
+        self.r.forward(self.params, self.sigma, self.bg, act, self.pre[v], self.snapshot)
         self.view_epoch[v] = self.epoch
         self._forget_labels()
         return act

@@ -49,7 +49,7 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert oit.workspace_bytes(cap, oit.camera_array([bad]), 1, tu) == 0
     # render_fwd with NULL splats fails before any device work
     rc = oit.lib.oit_render_fwd(None, None, None, cams, 1, ctypes.byref(cap), None, None, None, None, None,
-                                None, None, None, None, 0, ctypes.byref(tu), None)
+                                None, None, None, None, None, 0, ctypes.byref(tu), None)
     assert rc == -1
     rc = oit.lib.oit_update_active_set(None, 10, 0, 5, 0.0, None, None, 0, None, None, None, 0, None, None, 0, None)
     assert rc == -1
