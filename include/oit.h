@@ -165,6 +165,22 @@ oit_status oit_l1_loss(const float *image, const float *target, const oit_camera
                        int32_t n_views, float *grad_image, double *loss,
                        void *ws, size_t ws_bytes, oit_stream stream);
 
+/* Bytes of workspace that oit_l1_dssim_loss needs for these views; 0 on invalid input. */
+size_t oit_loss_workspace_bytes(const oit_camera *cams, int32_t n_views);
+
+/*
+ * The full 3DGS photometric loss, which the paper keeps (Sec. 5.1 "Implementation
+ * Details"): loss = sum_views (1 - lambda) mean_{3HW} |C - target|
+ *                            + lambda (1 - mean_{3HW} SSIM(C, target)),
+ * SSIM with an 11 x 11 Gaussian window (std 1.5, zero padding), C1 = 0.01^2,
+ * C2 = 0.03^2; lambda = 0.2 in 3DGS.  grad_image = dloss/dC.
+ * image, target, grad_image [V][3][H][W]; loss [1] device double (overwritten);
+ * ws of oit_loss_workspace_bytes(cams, n_views) bytes, 256-byte aligned.
+ */
+oit_status oit_l1_dssim_loss(const float *image, const float *target, const oit_camera *cams,
+                             int32_t n_views, float lambda, float *grad_image, double *loss,
+                             void *ws, size_t ws_bytes, oit_stream stream);
+
 /*
  * Backward pass (App. B, Eq. "oit_rendering_detail", then the chain rule through the
  * projection): given dL/dC for every view, write the gradient of every parameter of

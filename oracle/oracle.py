@@ -306,3 +306,96 @@ def fps(centres, s, start):
         picked.append(j)
         d = np.minimum(d, ((c - c[j]) ** 2).sum(axis=1))
     return picked
+
+
+# ----------------------------------------------------------------------------------
+# D-SSIM: the structural term of the 3DGS loss that the paper keeps (Sec. 5.1,
+# "Implementation Details": the loss and lambda_ssim follow 3DGS).  Reading: SSIM with an
+# 11 x 11 Gaussian window (std 1.5, normalised), zero padding ("same" size), constants
+# C1 = 0.01^2, C2 = 0.03^2, averaged over the 3HW values; D-SSIM = 1 - SSIM and the
+# loss (1 - lambda) L1 + lambda D-SSIM with lambda = 0.2, summed over views.
+# ----------------------------------------------------------------------------------
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def gaussian_window(size=11, std=1.5):
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-x * x / (2.0 * std * std))
+    return g / g.sum()
+
+
+def _filter(img, g):
+    """Zero-padded 'same' 2D filtering of [H][W] with the separable window g (rows, then
+    columns), written as explicit shifted sums."""
+    H, W = img.shape
+    r = len(g) // 2
+    tmp = np.zeros_like(img)
+    for k, gk in enumerate(g):
+        d = k - r
+        if d >= 0:
+            tmp[:, :W - d] += gk * img[:, d:]
+        else:
+            tmp[:, -d:] += gk * img[:, :W + d]
+    out = np.zeros_like(img)
+    for k, gk in enumerate(g):
+        d = k - r
+        if d >= 0:
+            out[:H - d, :] += gk * tmp[d:, :]
+        else:
+            out[-d:, :] += gk * tmp[:H + d, :]
+    return out
+
+
+def ssim_map(x, y):
+    """Per-pixel SSIM of two [3][H][W] images (float64)."""
+    g = gaussian_window()
+    S = np.zeros_like(np.asarray(x, np.float64))
+    for ch in range(3):
+        a = np.asarray(x[ch], np.float64)
+        b = np.asarray(y[ch], np.float64)
+        mx, my = _filter(a, g), _filter(b, g)
+        sxx = _filter(a * a, g) - mx * mx
+        syy = _filter(b * b, g) - my * my
+        sxy = _filter(a * b, g) - mx * my
+        S[ch] = ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / \
+                ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+    return S
+
+
+def dssim_loss_grad(x, y):
+    """D-SSIM = 1 - mean(SSIM) of image x against target y and its gradient wrt x.
+
+    With S = A1 A2 / (B1 B2), A1 = 2 mx my + C1, A2 = 2 (Exy - mx my) + C2,
+    B1 = mx^2 + my^2 + C1, B2 = Exx - mx^2 + Eyy - my^2 + C2 (E = filtered products):
+      dS/dmx = S (2my/A1 - 2my/A2 - 2mx/B1 + 2mx/B2),  dS/dExx = -S/B2,  dS/dExy = 2S/A2,
+    and dmean(S)/dx = [g * dS/dmx + 2x (g * dS/dExx) + y (g * dS/dExy)] / (3HW), the
+    filtering being its own adjoint for the symmetric window with zero padding."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    g = gaussian_window()
+    M = x.size
+    grad = np.zeros_like(x)
+    total = 0.0
+    for ch in range(3):
+        a, b = x[ch], y[ch]
+        mx, my = _filter(a, g), _filter(b, g)
+        Exx, Eyy, Exy = _filter(a * a, g), _filter(b * b, g), _filter(a * b, g)
+        A1 = 2 * mx * my + SSIM_C1
+        A2 = 2 * (Exy - mx * my) + SSIM_C2
+        B1 = mx * mx + my * my + SSIM_C1
+        B2 = (Exx - mx * mx) + (Eyy - my * my) + SSIM_C2
+        S = A1 * A2 / (B1 * B2)
+        total += S.sum()
+        dmx = S * (2 * my / A1 - 2 * my / A2 - 2 * mx / B1 + 2 * mx / B2)
+        dExx = -S / B2
+        dExy = 2 * S / A2
+        grad[ch] = -(_filter(dmx, g) + 2 * a * _filter(dExx, g) + b * _filter(dExy, g)) / M
+    return 1.0 - total / M, grad
+
+
+def l1_dssim_loss(image, target, lam=0.2):
+    """(1 - lambda) L1 + lambda D-SSIM of one view, and its gradient."""
+    l1, g1 = l1_loss(image, target)
+    ds, g2 = dssim_loss_grad(image, target)
+    return (1 - lam) * l1 + lam * ds, (1 - lam) * g1 + lam * g2

@@ -322,6 +322,62 @@ oit_status oit_l1_loss(const float *image, const float *target, const oit_camera
     return check_launch("oit_l1_loss");
 }
 
+namespace {
+struct LossPlan {
+    size_t cams, acc, maps, total;
+    int64_t total_px;
+    int tiles16;
+};
+
+oit_status loss_plan(const oit_camera *cams, int32_t n_views, LossPlan &lp, Plan &p)
+{
+    oit_capacity cap{1, 1, 0};
+    oit_tuning tu{16, 64, 1};
+    oit_status st = make_plan(&cap, cams, n_views, &tu, p);
+    if (st != OIT_OK) return st;
+    lp.total_px = p.total_px;
+    lp.tiles16 = p.T;
+    size_t o = align256(4);
+    lp.cams = o;
+    o = align256(o + sizeof(CamDev) * kMaxViews);
+    lp.acc = o;
+    o = align256(o + 2 * sizeof(double));
+    lp.maps = o;
+    o = align256(o + 9 * sizeof(float) * (size_t)p.total_px);
+    lp.total = o;
+    return OIT_OK;
+}
+}  // namespace
+
+size_t oit_loss_workspace_bytes(const oit_camera *cams, int32_t n_views)
+{
+    LossPlan lp;
+    Plan p;
+    if (loss_plan(cams, n_views, lp, p) != OIT_OK) return 0;
+    return lp.total;
+}
+
+oit_status oit_l1_dssim_loss(const float *image, const float *target, const oit_camera *cams, int32_t n_views,
+                             float lambda, float *grad_image, double *loss, void *ws, size_t ws_bytes,
+                             oit_stream stream)
+{
+    LossPlan lp;
+    Plan p;
+    oit_status st;
+    if ((st = loss_plan(cams, n_views, lp, p)) != OIT_OK) return st;
+    if (!image || !target || !grad_image || !loss) return fail(OIT_ERR_INVALID, "oit_l1_dssim_loss: NULL buffer");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(OIT_ERR_INVALID, "lambda must be in [0, 1]");
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < lp.total) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lp.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    CamDev *dcams = (CamDev *)(w + lp.cams);
+    upload_cams(p.cams_host, n_views, dcams, s);
+    launch_l1_dssim(dcams, n_views, lp.total_px, lp.tiles16, image, target, lambda, grad_image, loss,
+                    (float *)(w + lp.maps), (double *)(w + lp.acc), s);
+    return check_launch("oit_l1_dssim_loss");
+}
+
 oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const float *bg, const oit_camera *cams,
                           int32_t n_views, const oit_capacity *cap, const int32_t *active_idx,
                           const int32_t *n_active, const int32_t *delta_idx, const int8_t *delta_sign,

@@ -85,6 +85,10 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
                            const GradPtrs &g, double *grad_sigma, float *score, const float eps[6],
                            hipStream_t s);
 
+void launch_l1_dssim(const CamDev *cams, int n_views, int64_t total_px, int tiles16, const float *image,
+                     const float *target, float lambda, float *grad, double *loss, float *maps, double *acc,
+                     hipStream_t s);
+
 struct SelectBuffers {
     int32_t *status;
     uint32_t *state;      // [8]: prefix, k_remaining, digit results

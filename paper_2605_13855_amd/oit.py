@@ -73,6 +73,10 @@ def _load():
     L.oit_read_status.argtypes = [P, SZ, P, P]
     L.oit_clear_status.argtypes = [P, SZ, P]
     L.oit_read_counters.argtypes = [P, SZ, P, P, I32, P, P, P]
+    L.oit_loss_workspace_bytes.argtypes = [P, I32]
+    L.oit_loss_workspace_bytes.restype = SZ
+    L.oit_l1_dssim_loss.argtypes = [P, P, P, I32, F, P, P, P, SZ, P]
+    L.oit_l1_dssim_loss.restype = ctypes.c_int
     L.oit_label_delta.argtypes = [P, P, I64, P, I64, P, P, P, I64, P, P, SZ, P]
     L.oit_fps_views.argtypes = [P, I32, I32, I32, P]
     L.oit_timing_enable.argtypes = [I32]
@@ -162,6 +166,16 @@ def l1_loss(image, target, cams_arr, n_views, grad_image, loss, ws, stream=None)
     rc = lib.oit_l1_loss(_ptr(image), _ptr(target), cams_arr, n_views, _ptr(grad_image), _ptr(loss),
                          _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "oit_l1_loss")
+
+
+def loss_workspace_bytes(cams_arr, n_views) -> int:
+    return int(lib.oit_loss_workspace_bytes(cams_arr, int(n_views)))
+
+
+def l1_dssim_loss(image, target, cams_arr, n_views, lam, grad_image, loss, ws, stream=None):
+    rc = lib.oit_l1_dssim_loss(_ptr(image), _ptr(target), cams_arr, int(n_views), float(lam), _ptr(grad_image),
+                               _ptr(loss), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "oit_l1_dssim_loss")
 
 
 def render_bwd(splats: Splats, sigma, bg_host, cams_arr, n_views, cap: Capacity, active_idx, n_active,
