@@ -91,10 +91,16 @@ typedef struct {
     int64_t stride;
 } oit_grads;
 
+#define OIT_BWD_PER_SPLAT 0 /* one splat per lane over its tile's pixels (Sec. 4.2) */
+#define OIT_BWD_PER_PIXEL 1 /* one pixel per thread, an atomic per contributing pair
+                               (the 3DGS baseline of Tab. "ablation", for comparison) */
+
 typedef struct {
     int32_t tile;           /* tile edge in pixels: 8, 16 or 32 */
     int32_t batch;          /* splat records staged in LDS per forward batch: 32..256 */
     int64_t pair_capacity;  /* capacity of the (tile, splat) entry list */
+    int32_t bwd_mode;       /* OIT_BWD_PER_SPLAT (default) or OIT_BWD_PER_PIXEL */
+    int32_t reserved;       /* 0 */
 } oit_tuning;               /* (host) */
 
 /* Sizes that fix the workspace of render_fwd / render_bwd (host). */

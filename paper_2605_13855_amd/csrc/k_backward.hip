@@ -278,10 +278,110 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------------
+// raster backward, per-pixel form (the 3DGS baseline of the paper's ablation): one
+// thread per pixel walks its tile's active entries (staged through LDS like the
+// forward) and adds the 10 screen-space partials of every contributing pair to the
+// splat with one atomic each.  Same partials as k_raster_bwd; kept for comparison.
+// ---------------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(BwdArgs a)
+{
+    constexpr int NT = S * S < 256 ? S * S : 256;
+    constexpr int PPT = S * S / NT;
+    constexpr int B = 64;
+    __shared__ float4 s_rec[B * 3];
+    __shared__ uint32_t s_r[B];
+    const int tile = blockIdx.x;
+    const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
+    const CamDev &cam = a.b.cams[v];
+    const int lt = tile - cam.tile_base;
+    const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+    float px[PPT], py[PPT], A0[PPT], A1[PPT], A2[PPT], s1[PPT], Bc[PPT];
+    bool in[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int li = threadIdx.x + p * NT;
+        const int x = tx * S + li % S, y = ty * S + li / S;
+        px[p] = (float)x + 0.5f;
+        py[p] = (float)y + 0.5f;
+        in[p] = x < cam.W && y < cam.H;
+        float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (in[p]) {
+            const size_t gp = (size_t)cam.pix_base + (size_t)y * cam.W + x;
+            c0 = a.b.pixconst[2 * gp];
+            c1 = a.b.pixconst[2 * gp + 1];
+        }
+        A0[p] = c0.x;
+        A1[p] = c0.y;
+        A2[p] = c0.z;
+        s1[p] = c0.w;
+        Bc[p] = c1.x;
+    }
+    const uint64_t cap = (uint64_t)a.b.pair_cap;
+    const uint64_t off = a.b.tile_off[tile];
+    uint64_t na = a.b.cnt_a[tile];
+    if (off + na > cap) na = off < cap ? cap - off : 0;
+    const Rec *recv = a.b.rec + (size_t)v * a.b.Rcap;
+    for (uint64_t base = 0; base < na; base += B) {
+        const int cnt = (int)(na - base < (uint64_t)B ? na - base : (uint64_t)B);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += NT) {
+            const uint32_t ri = a.b.entries[off + base + j];
+            const bool ok = ri < a.b.Acap;
+            const Rec r = ok ? recv[ri] : Rec{{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            s_rec[3 * j] = r.a;
+            s_rec[3 * j + 1] = r.b;
+            s_rec[3 * j + 2] = r.c;
+            s_r[j] = ok ? ri : 0u;
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+            float *dst = a.b.sgrad + ((size_t)v * a.b.Acap + s_r[j]) * 10;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (!in[p]) continue;
+                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
+                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
+                if (e < kLog2AlphaMin) continue;
+                const bool capped = e > kLog2AlphaMax;
+                const float al = capped ? kAlphaMax : __builtin_amdgcn_exp2f(e);
+                const float w = rc.y;
+                const float diff = fmaf(A0[p], rb.z, fmaf(A1[p], rb.w, A2[p] * rc.x)) - s1[p];
+                const float aw = al * w;
+                unsafeAtomicAdd(dst + 6, A0[p] * aw);
+                unsafeAtomicAdd(dst + 7, A1[p] * aw);
+                unsafeAtomicAdd(dst + 8, A2[p] * aw);
+                unsafeAtomicAdd(dst + 9, al * diff);
+                if (!capped) {
+                    const float dLde = fmaf(w, diff, Bc[p] * __builtin_amdgcn_rcpf(1.f - al)) * al * kLn2;
+                    const float ex = dLde * dx, ey = dLde * dy;
+                    unsafeAtomicAdd(dst + 0, -fmaf(2.f * ra.z, ex, ra.w * ey));
+                    unsafeAtomicAdd(dst + 1, -fmaf(ra.w, ex, 2.f * rb.x * ey));
+                    unsafeAtomicAdd(dst + 2, ex * dx);
+                    unsafeAtomicAdd(dst + 3, ex * dy);
+                    unsafeAtomicAdd(dst + 4, ey * dy);
+                    unsafeAtomicAdd(dst + 5, dLde);
+                }
+            }
+        }
+    }
+}
+
 bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s)
 {
     (void)rl;
     BwdArgs a{b};
+    if (b.bwd_mode == OIT_BWD_PER_PIXEL) {
+        if (b.T == 0) return true;
+        switch (b.tile) {
+        case 8: hipLaunchKernelGGL(k_raster_bwd_pixel<8>, dim3(b.T), dim3(64), 0, s, a); return true;
+        case 16: hipLaunchKernelGGL(k_raster_bwd_pixel<16>, dim3(b.T), dim3(256), 0, s, a); return true;
+        case 32: hipLaunchKernelGGL(k_raster_bwd_pixel<32>, dim3(b.T), dim3(256), 0, s, a); return true;
+        default: return false;
+        }
+    }
     const dim3 grid(1024), block(256);
     switch (b.tile) {
     case 8: hipLaunchKernelGGL(k_raster_bwd<8>, grid, block, 0, s, a); return true;

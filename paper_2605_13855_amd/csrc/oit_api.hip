@@ -80,6 +80,8 @@ oit_status check_tuning(const oit_tuning *tu)
         return fail(OIT_ERR_INVALID, "tuning.tile = %d not in {8, 16, 32}", tu->tile);
     if (tu->batch != 32 && tu->batch != 64 && tu->batch != 128 && tu->batch != 256)
         return fail(OIT_ERR_INVALID, "tuning.batch = %d not in {32, 64, 128, 256}", tu->batch);
+    if (tu->bwd_mode != OIT_BWD_PER_SPLAT && tu->bwd_mode != OIT_BWD_PER_PIXEL)
+        return fail(OIT_ERR_INVALID, "tuning.bwd_mode = %d unknown", tu->bwd_mode);
     if (tu->pair_capacity <= 0 || tu->pair_capacity >= 0xffffffffLL)
         return fail(OIT_ERR_INVALID, "tuning.pair_capacity = %lld outside [1, 2^32 - 1)",
                     (long long)tu->pair_capacity);
@@ -173,6 +175,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.n_views = n_views;
     b.T = p.T;
     b.tile = tu->tile;
+    b.bwd_mode = tu->bwd_mode;
     b.total_px = p.total_px;
     b.pair_cap = tu->pair_capacity;
     b.Acap = p.Acap;
@@ -312,7 +315,7 @@ oit_status oit_l1_loss(const float *image, const float *target, const oit_camera
     const size_t need = align256(4) + sizeof(CamDev) * kMaxViews;
     if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     oit_capacity cap{1, 1, 0};
-    oit_tuning tu{16, 64, 1};
+    oit_tuning tu{16, 64, 1, OIT_BWD_PER_SPLAT, 0};
     Plan p;
     if ((st = make_plan(&cap, cams, n_views, &tu, p)) != OIT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -332,7 +335,7 @@ struct LossPlan {
 oit_status loss_plan(const oit_camera *cams, int32_t n_views, LossPlan &lp, Plan &p)
 {
     oit_capacity cap{1, 1, 0};
-    oit_tuning tu{16, 64, 1};
+    oit_tuning tu{16, 64, 1, OIT_BWD_PER_SPLAT, 0};
     oit_status st = make_plan(&cap, cams, n_views, &tu, p);
     if (st != OIT_OK) return st;
     lp.total_px = p.total_px;

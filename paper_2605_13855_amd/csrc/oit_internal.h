@@ -50,7 +50,7 @@ struct Buffers {
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
     float *sgrad;                               // [V][Acap][10]
     float4 *pixconst;                           // [total_px][2]
-    int n_views, T, tile;
+    int n_views, T, tile, bwd_mode;
     int64_t total_px, pair_cap;
     int64_t Acap, Rcap;                         // record stride: Rcap per view
 };

@@ -42,8 +42,13 @@ class Grads(ctypes.Structure):
     _fields_ = [(g, ctypes.c_void_p) for g, _ in GROUPS] + [("stride", ctypes.c_int64)]
 
 
+BWD_PER_SPLAT = 0
+BWD_PER_PIXEL = 1
+
+
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("pair_capacity", ctypes.c_int64),
+                ("bwd_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Capacity(ctypes.Structure):

@@ -63,7 +63,7 @@ class Renderer:
         if pair_capacity is None:
             pair_capacity = min(estimate_pairs(self.cap.active_capacity + self.cap.delta_capacity,
                                                self.cams, tile), 2 ** 32 - 2)
-        self.tuning = oit.Tuning(int(tile), int(batch), int(pair_capacity))
+        self.tuning = oit.Tuning(int(tile), int(batch), int(pair_capacity), oit.BWD_PER_SPLAT, 0)
         self._alloc_ws()
         dev = self.device
         self._image_buf = torch.zeros(3 * self.total_px, device=dev)
@@ -97,9 +97,10 @@ class Renderer:
         self.image = self._image_buf[:3 * self.total_px]
         self.pixstate = self._pixstate_buf[:5 * self.total_px]
 
-    def set_tuning(self, tile=None, batch=None, pair_capacity=None):
+    def set_tuning(self, tile=None, batch=None, pair_capacity=None, bwd_mode=None):
         self.tuning = oit.Tuning(int(tile or self.tuning.tile), int(batch or self.tuning.batch),
-                                 int(pair_capacity or self.tuning.pair_capacity))
+                                 int(pair_capacity or self.tuning.pair_capacity),
+                                 int(self.tuning.bwd_mode if bwd_mode is None else bwd_mode), 0)
         self._alloc_ws()
 
     def views(self, flat: torch.Tensor, planes: int):

@@ -27,11 +27,13 @@ def log(msg):
 
 
 def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True, windows=None, seed=0,
-               sigma_atol=0.0):
+               sigma_atol=0.0, bwd_mode=0):
     """Render sc densely on the GPU and in the oracle; compare image, state and grads."""
     params = params_to_device(sc.params)
     sigma = torch.tensor([sc.sigma], device=DEV)
     r = Renderer(sc.cameras, sc.n, tile=tile, batch=batch)
+    if bwd_mode:
+        r.set_tuning(bwd_mode=bwd_mode)
     r.fit_pair_capacity(params, sigma, sc.background)
     r.forward(params, sigma, sc.background)
     torch.cuda.synchronize()
@@ -86,6 +88,15 @@ def test_tiny_dense_parity(tile, batch):
     log(f"tiny dense parity tile={tile} batch={batch}")
     sc = scenes.make_scene(1)
     dense_case(sc, tile, batch)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_per_pixel_backward_matches_oracle(tile):
+    """The per-pixel backward (atomics per pair, the 3DGS baseline of the paper's
+    ablation) gives the same gradients as the oracle."""
+    log(f"per-pixel backward, tile={tile}")
+    sc = scenes.random_scene(25, 2500, 72, 56, n_views=2, mean_range=1.0)
+    dense_case(sc, tile, 64, bwd_mode=1)
 
 
 def test_ragged_image_and_tiles():
