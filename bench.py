@@ -121,6 +121,37 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     return out
 
 
+def ablation(scene, steps, tile, batch):
+    """Synthetic analogue of the paper's backward ablation (Tab. "ablation"): the dense
+    iteration with the per-splat backward against the per-pixel backward that adds an
+    atomic per contributing pair (the 3DGS design), on the same tile lists."""
+    import torch
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd.render import ActiveSetTrainer
+    out = {}
+    for name, mode in (("per_splat", oit.BWD_PER_SPLAT), ("per_pixel_atomics", oit.BWD_PER_PIXEL)):
+        t = ActiveSetTrainer(scene, tile=tile, batch=batch, dense=True)
+        t.r.set_tuning(bwd_mode=mode)
+        prime(t)
+        oit.timing_enable(True)
+        ms, bwd = [], []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t.iteration()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            bwd.append(oit.timing_read()[1])
+        oit.timing_enable(False)
+        out[name] = {"ms_per_iter": round(statistics.median(ms), 4), "raster_bwd_ms": round(statistics.median(bwd), 4)}
+        log(f"ablation {name}: {out[name]}")
+        del t
+        torch.cuda.empty_cache()
+    out["bwd_speedup_per_splat"] = round(out["per_pixel_atomics"]["raster_bwd_ms"] / out["per_splat"]["raster_bwd_ms"], 3)
+    return out
+
+
 def cpu_baseline(scene, budget_s=20.0):
     """The FP64 oracle, single-threaded, on a window of view 0 (all splats), fwd + bwd."""
     import numpy as np
@@ -163,6 +194,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log-scale-mu", type=float, default=-3.5)
     ap.add_argument("--eager", action="store_true", help="launch every step eagerly instead of a HIP graph")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark line, time the per-splat against the per-pixel backward "
+                         "(dense; default config 2)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -186,6 +220,13 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.copy_mb} MiB read + {args.copy_mb} MiB written")
         del src, dst
+    if args.ablation:
+        cfg = args.config if "--config" in sys.argv else 2
+        scene = scenes.make_scene(cfg)
+        res = ablation(scene, args.steps, args.tile, args.batch)
+        print(json.dumps({"ablation": res, "config": {"workload": f"config {cfg}: {scene.n} splats, "
+                          f"{len(scene.cameras)} view(s), dense fwd+bwd, L1"}}), flush=True)
+        return
     log(f"building scene config {args.config}")
     scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
     px = sum(c.width * c.height for c in scene.cameras)
