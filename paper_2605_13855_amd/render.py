@@ -154,6 +154,27 @@ class Renderer:
         return need
 
 
+class PhotometricLoss:
+    """The training loss: "l1" (the benchmark configurations) or "l1_dssim", the 3DGS
+    loss (1 - lambda) L1 + lambda D-SSIM that the paper keeps (Sec. 5.1), lambda = 0.2.
+    Owns the D-SSIM workspace and grows it with the batch."""
+
+    def __init__(self, kind="l1", lam=0.2, device="cuda"):
+        if kind not in ("l1", "l1_dssim"):
+            raise ValueError(f"unknown loss {kind}")
+        self.kind, self.lam, self.device = kind, float(lam), torch.device(device)
+        self.ws = None
+
+    def __call__(self, renderer, image, target, grad, loss):
+        if self.kind == "l1":
+            oit.l1_loss(image, target, renderer.cams_arr, renderer.n_views, grad, loss, renderer.ws)
+            return
+        nb = oit.loss_workspace_bytes(renderer.cams_arr, renderer.n_views)
+        if self.ws is None or self.ws.numel() < nb:
+            self.ws = _aligned_workspace(nb, self.device)
+        oit.l1_dssim_loss(image, target, renderer.cams_arr, renderer.n_views, self.lam, grad, loss, self.ws)
+
+
 def new_grads(n_rows: int, device) -> dict:
     return {g: torch.zeros((c, n_rows), device=device) for g, c in GROUPS}
 
@@ -197,8 +218,10 @@ class ActiveSetTrainer:
     """Device state and the launch sequence of one training iteration."""
 
     def __init__(self, scene, fraction=0.05, lr=1e-3, sigma_lr=1e-3, betas=(0.9, 0.999), eps=1e-15,
-                 tile=16, batch=64, pair_capacity=None, dense=False, device="cuda", delta_capacity=None):
+                 tile=16, batch=64, pair_capacity=None, dense=False, device="cuda", delta_capacity=None,
+                 loss="l1"):
         self.device = torch.device(device)
+        self.loss_fn = PhotometricLoss(loss, device=device)
         dev = self.device
         self.params = params_to_device(scene.params, dev)
         self.n = self.params["mean"].shape[1]
@@ -251,8 +274,7 @@ class ActiveSetTrainer:
     def forward_loss(self):
         pre = None if self.dense else self.pre
         self.r.forward(self.params, self.sigma, self.bg, self._active(), pre)
-        oit.l1_loss(self.r.image, self.target, self.r.cams_arr, self.r.n_views, self.grad_image, self.loss,
-                    self.r.ws)
+        self.loss_fn(self.r, self.r.image, self.target, self.grad_image, self.loss)
 
     def backward(self):
         pre = None if self.dense else self.pre
@@ -281,7 +303,7 @@ class ActiveSetTrainer:
         r.fit_pair_capacity(self.params, self.sigma, self.bg)
         r.forward(self.params, self.sigma, self.bg)
         gi = torch.zeros_like(self.grad_image)
-        oit.l1_loss(r.image, self.target, r.cams_arr, r.n_views, gi, self.loss, r.ws)
+        self.loss_fn(r, r.image, self.target, gi, self.loss)
         g = new_grads(self.n, self.device)
         gsig = torch.zeros(1, dtype=torch.float64, device=self.device)
         r.backward(self.params, self.sigma, self.bg, gi, g, gsig, score=self.score)

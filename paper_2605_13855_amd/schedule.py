@@ -7,7 +7,8 @@
   ||dL/dtheta_g|| / eps_g, and the splats with score > 1 become active.
 * Every iteration renders one training view (views are drawn in shuffled passes, as
   3DGS does) with the active splats against that view's pre-rendered buffer, takes the
-  L1 loss, back-propagates to the active rows, and applies sparse Adam and Adam on sigma.
+  3DGS loss (L1 + D-SSIM by default), back-propagates to the active rows, and applies
+  sparse Adam and Adam on sigma.
 * Pre-rendered buffers are brought up to date lazily, when their view is next used
   (Sec. 4.1 "Implementation Details"): a buffer one update behind receives the label
   changes between its labels and the current ones in the same pass that renders it.
@@ -26,13 +27,14 @@ import numpy as np
 import torch
 
 from . import oit
-from .render import Renderer, _aligned_workspace, new_grads, params_to_device
+from .render import PhotometricLoss, Renderer, _aligned_workspace, new_grads, params_to_device
 
 
 class PaperScheduleTrainer:
     def __init__(self, scene, eps, interval=500, n_sub=30, lr=1e-3, sigma_lr=1e-3, betas=(0.9, 0.999),
-                 adam_eps=1e-15, tile=16, batch=64, seed=0, device="cuda"):
+                 adam_eps=1e-15, tile=16, batch=64, seed=0, device="cuda", loss="l1_dssim"):
         self.device = torch.device(device)
+        self.loss_fn = PhotometricLoss(loss, device=device)
         dev = self.device
         self.params = params_to_device(scene.params, dev)
         self.n = self.params["mean"].shape[1]
@@ -102,7 +104,7 @@ class PaperScheduleTrainer:
         r.forward(self.params, self.sigma, self.bg)
         target = torch.cat([self.targets[i] for i in views])
         gi = torch.zeros_like(target)
-        oit.l1_loss(r.image, target, r.cams_arr, r.n_views, gi, self.loss, r.ws)
+        self.loss_fn(r, r.image, target, gi, self.loss)
         g = new_grads(self.n, self.device)
         gsig = torch.zeros(1, dtype=torch.float64, device=self.device)
         r.backward(self.params, self.sigma, self.bg, gi, g, gsig, score=self.score, eps=self.eps)
@@ -161,7 +163,7 @@ class PaperScheduleTrainer:
         v = self.next_view()
         act = self.render_view(v)
         gi = self.grad_image[:3 * self.cams[v].width * self.cams[v].height]
-        oit.l1_loss(self.r.image, self.targets[v], self.r.cams_arr, 1, gi, self.loss, self.r.ws)
+        self.loss_fn(self.r, self.r.image, self.targets[v], gi, self.loss)
         self.r.backward(self.params, self.sigma, self.bg, gi, self.grads, self.grad_sigma, act, self.pre[v])
         gs = oit.grads_struct(self.grads, self.n)
         oit.sparse_adam_step(self.params, gs, self.m, self.v, self.active_idx, self.n_active, self.n, self.lr,

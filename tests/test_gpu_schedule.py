@@ -60,11 +60,11 @@ def test_threshold_activeness_on_subsampled_views():
     """The active set after an update is {score > 1} with the score of the summed
     gradient over the FPS views; compared with the oracle away from the threshold."""
     sc = small_scene()
-    probe = PaperScheduleTrainer(sc, eps=[1.0] * 6, interval=100, n_sub=3, seed=1)
+    probe = PaperScheduleTrainer(sc, eps=[1.0] * 6, interval=100, n_sub=3, seed=1, loss="l1")
     probe.update_active_set()
     s = to_np(probe.score)
     eps = [float(np.quantile(s, 0.7))] * 6          # about 30% active
-    t = PaperScheduleTrainer(sc, eps=eps, interval=100, n_sub=3, seed=1)
+    t = PaperScheduleTrainer(sc, eps=eps, interval=100, n_sub=3, seed=1, loss="l1")
     t.update_active_set()
     torch.cuda.synchronize()
     views = t.last_update_views
