@@ -171,9 +171,11 @@ def cpu_baseline(scene, budget_s=20.0):
         dt = time.perf_counter() - t0
         total_pairs, total_s = r["pairs"], dt
         log(f"cpu oracle: window {side}x{side}: {r['pairs']:.3e} pairs, {dt:.2f} s")
-        if dt > budget_s / 4 or side >= 512:
+        if dt > budget_s / 2 or side >= min(512, cam.width, cam.height) - 1:
             break
-        side = min(512, int(side * math.sqrt(budget_s / 2 / max(dt, 1e-3))))
+        # the work grows with the window area; aim the next window at the budget
+        side = min(512, cam.width, cam.height, int(side * math.sqrt(budget_s / max(dt, 1e-3))))
+        side -= side % 2
     return {"value": total_pairs / total_s, "unit": "splat-pixel evals/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle fwd+bwd, view 0 ({cam.width}x{cam.height}), all "
                       f"{scene.n} splats, centre window {side}x{side}: {total_pairs} contributing pairs "

@@ -39,11 +39,22 @@ struct LossArgs {
     double *loss;
 };
 
+// Grid of the per-pixel kernels: a grid-stride loop over the batch's pixels with at most
+// kPixBlocks blocks, so that the one FP64 atomic per block onto a single address stays
+// a few thousand operations instead of one per 256 pixels.
+constexpr int64_t kPixBlocks = 2048;
+
+static unsigned pixel_blocks(int64_t total_px)
+{
+    const int64_t b = (total_px + 255) / 256;
+    return (unsigned)(b < kPixBlocks ? b : kPixBlocks);
+}
+
 __global__ __launch_bounds__(256) void k_l1_loss(LossArgs a)
 {
-    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (gp < a.b.total_px) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < a.b.total_px; gp += stride) {
         const int v = view_of_pixel(a.b.cams, a.b.n_views, gp);
         const CamDev &cam = a.b.cams[v];
         const size_t HW = (size_t)cam.W * cam.H;
@@ -66,7 +77,7 @@ void launch_l1_loss(const Buffers &b, const float *image, const float *target, f
 {
     fill_f64(loss, 1, 0.0, s);
     LossArgs a{b, image, target, grad, loss};
-    const unsigned blocks = (unsigned)((b.total_px + 255) / 256);
+    const unsigned blocks = pixel_blocks(b.total_px);
     if (blocks) hipLaunchKernelGGL(k_l1_loss, dim3(blocks), dim3(256), 0, s, a);
 }
 
@@ -89,9 +100,9 @@ struct PixArgs {
 
 __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
 {
-    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (gp < a.b.total_px) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < a.b.total_px; gp += stride) {
         const int v = view_of_pixel(a.b.cams, a.b.n_views, gp);
         const CamDev &cam = a.b.cams[v];
         const size_t HW = (size_t)cam.W * cam.H;
@@ -106,13 +117,13 @@ __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
         const float A0 = g[0] * k, A1 = g[1] * k, A2 = g[2] * k;
         const float s1 = A0 * F[0] + A1 * F[1] + A2 * F[2];
         const float B = T * (g[0] * (F[0] - a.bg0) + g[1] * (F[1] - a.bg1) + g[2] * (F[2] - a.bg2));
-        a.b.pixconst[2 * gp] = make_float4(A0, A1, A2, s1);
-        a.b.pixconst[2 * gp + 1] = make_float4(B, 0.f, 0.f, 0.f);
+        a.b.pixconst[gp] = make_float4(A0, A1, A2, -s1);
+        a.b.pixB[gp] = B;
         if (a.pre) {
             const float *pr = a.pre + 9 * pb + local;
             const float Q1 = pr[7 * HW];
             const double sig = (double)*a.sigma;
-            acc = ((double)A0 * ((double)pr[3 * HW] - (double)F[0] * Q1) +
+            acc += ((double)A0 * ((double)pr[3 * HW] - (double)F[0] * Q1) +
                    (double)A1 * ((double)pr[4 * HW] - (double)F[1] * Q1) +
                    (double)A2 * ((double)pr[5 * HW] - (double)F[2] * Q1)) / (sig * sig);
         }
@@ -124,156 +135,213 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
                      const float *grad_image, const float *pixstate, double *grad_sigma, hipStream_t s)
 {
     PixArgs a{b, sigma, bg[0], bg[1], bg[2], pre, grad_image, pixstate, grad_sigma};
-    const unsigned blocks = (unsigned)((b.total_px + 255) / 256);
+    const unsigned blocks = pixel_blocks(b.total_px);
     if (blocks) hipLaunchKernelGGL(k_pixconst, dim3(blocks), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------------
-// raster backward: one wave per work item = (tile, 64 active entries); one splat per
-// lane.  The wave stages 64 pixels' constants in its own LDS slice (every lane
-// fetches one pixel once) and then every lane walks those 64 pixels in turn, so all
-// per-splat sums stay in registers; they are added to the per-(view, record)
-// screen-space gradient once per work item.
+// raster backward (the paper's per-splat backward, Sec. 4.2): one wave per work item
+// = (tile, 64 active entries), one splat per lane.  The tile is walked in 8 x 8 pixel
+// groups and a group that no lane's footprint box reaches is skipped.  For each
+// remaining group the wave stages the 64 pixels' constants in its LDS slice (one
+// pixel per lane; the next group's are fetched from memory while the current one is
+// processed), then every lane walks the 64 pixels column by column and reads each
+// pixel's constants as a uniform LDS broadcast.  Per splat, the colour and weight
+// sums and the moments of dL/de over the pixel offsets stay in registers; they give
+// the 10 screen-space partials once per work item, added to the per-(view, record)
+// gradient with one atomic per component.
+//
+// The work items are split into 8 contiguous ranges, one per XCD, so that the waves
+// that share a tile's pixel constants share an L2; a wave whose range is drained
+// moves on to the next range.
+//
 // Screen-space gradient layout (10 floats): d/dmx, d/dmy, d/dqa, d/dqb, d/dqc, d/dlo,
-// d/dc (rgb), d/dw — q* and lo as in the record.
+// d/dc (rgb), d/dw -- q* and lo as in the record.
 // ---------------------------------------------------------------------------------
 struct BwdArgs {
     Buffers b;
 };
 
-template <int S>
-__global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a)
+constexpr int kGroup = 8;   // pixel group edge of the backward
+
+// tile of every backward work item (a chunk of 64 active entries of one tile)
+__global__ __launch_bounds__(256) void k_chunk_map(Buffers b)
 {
-    __shared__ float4 s_pc[4][64][2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
-    const uint64_t cap = (uint64_t)a.b.pair_cap;
-    constexpr int GROUPS = S * S / 64;
-    constexpr int ROWS = 64 / S > 0 ? 64 / S : 1;   // tile rows per group (S >= 8)
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.T) return;
+    const uint32_t c1 = min(b.chunk_off[t + 1], b.max_chunks);
+    for (uint32_t c = b.chunk_off[t]; c < c1; ++c) b.chunk_tile[c] = (uint32_t)t;
+}
 
+template <int S>
+__device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
+                                         float4 (*s_c)[64], float (*s_B)[64])
+{
+    constexpr int GX = S / kGroup;   // groups per tile edge
+    const uint64_t cap = (uint64_t)b.pair_cap;
+    const int tile = (int)b.chunk_tile[item];
+    const uint32_t chunk = item - b.chunk_off[tile];
+    const int v = view_of_tile(b.cams, b.n_views, tile);
+    const CamDev &cam = b.cams[v];
+    const int lt = tile - cam.tile_base;
+    const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+    const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
+    const uint64_t off = b.tile_off[tile];
+    uint64_t na = b.cnt_a[tile];
+    if (off + na > cap) na = off < cap ? cap - off : 0;
+    const uint64_t j = (uint64_t)chunk * 64 + lane;
+    const uint32_t rj = j < na ? b.entries[off + j] : 0u;
+    const bool valid = j < na && rj < b.Acap;
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = make_float4(0.f, -1e30f, 0.f, 0.f),
+           rc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        const Rec rr = b.rec[(size_t)v * b.Rcap + rj];
+        ra = rr.a;
+        rb = rr.b;
+        rc = rr.c;
+    }
+    const float dx0 = x0 - ra.x, dy0 = y0 - ra.y;
+    const float qa = ra.z, qb = ra.w, qc = rb.x, lo = rb.y;
+    const float cr = rb.z, cg = rb.w, cb = rc.x, w = rc.y;
+
+    // footprint half-extents of the (widened) alpha >= 1/255 level set, in pixels
+    float hx = -1.f, hy = -1.f;
+    if (valid) {
+        const float A = -qa, B = -0.5f * qb, C = -qc;
+        const float det = A * C - B * B;
+        const float tau = (lo - kLog2AlphaMin) * 1.001f + 1e-3f;
+        if (tau > 0.f && det > 0.f) {
+            hx = sqrtf(tau * C / det) + 0.01f;
+            hy = sqrtf(tau * A / det) + 0.01f;
+        }
+    }
+    // bit g: some lane's footprint box reaches group g (pixel offsets [g0, g0 + 7])
+    uint32_t mask = 0;
+#pragma unroll
+    for (int g = 0; g < GX * GX; ++g) {
+        const float gx0 = dx0 + (float)((g % GX) * kGroup), gy0 = dy0 + (float)((g / GX) * kGroup);
+        const bool hit = hx >= 0.f && gx0 <= hx && gx0 + (float)(kGroup - 1) >= -hx && gy0 <= hy &&
+                         gy0 + (float)(kGroup - 1) >= -hy;
+        if (__ballot(hit)) mask |= 1u << g;
+    }
+    if (mask == 0) return;
+
+    // this lane's pixel when staging a group's constants
+    const int sx = lane % kGroup, sy = lane / kGroup;
+    const size_t pb = (size_t)cam.pix_base;
+    auto fetch = [&](int g, float4 &c, float &Bv) {
+        const int x = tx * S + (g % GX) * kGroup + sx, y = ty * S + (g / GX) * kGroup + sy;
+        c = make_float4(0.f, 0.f, 0.f, 0.f);
+        Bv = 0.f;
+        if (x < cam.W && y < cam.H) {
+            const size_t gp = pb + (size_t)y * cam.W + x;
+            c = b.pixconst[gp];
+            Bv = b.pixB[gp];
+        }
+    };
+
+    float g_cr = 0.f, g_cg = 0.f, g_cb = 0.f, g_w = 0.f;
+    // moments of dL/de (without the ln 2 of d alpha / de) over the pixel offsets
+    float m0 = 0.f, m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
+    int g = __builtin_ctz(mask);
+    mask &= mask - 1;
+    float4 nc;
+    float nB;
+    fetch(g, nc, nB);
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(&a.b.counters[CNT_BWD_WORK], 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= total) break;
-        int lo_t = 0, hi_t = a.b.T;
-        while (hi_t - lo_t > 1) {
-            const int mid = (lo_t + hi_t) >> 1;
-            if (a.b.chunk_off[mid] <= item) lo_t = mid;
-            else hi_t = mid;
+        s_c[wave][lane] = nc;
+        s_B[wave][lane] = nB;
+        int gn = -1;
+        if (mask) {
+            gn = __builtin_ctz(mask);
+            mask &= mask - 1;
+            fetch(gn, nc, nB);
         }
-        const int tile = lo_t;
-        const uint32_t chunk = item - a.b.chunk_off[tile];
-        const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
-        const CamDev &cam = a.b.cams[v];
-        const int lt = tile - cam.tile_base;
-        const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
-        const uint64_t off = a.b.tile_off[tile];
-        uint64_t na = a.b.cnt_a[tile];
-        if (off + na > cap) na = off < cap ? cap - off : 0;
-        const uint64_t j = (uint64_t)chunk * 64 + lane;
-        const uint32_t rj = j < na ? a.b.entries[off + j] : 0u;
-        const bool valid = j < na && rj < a.b.Acap;
-        uint32_t r = 0;
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = make_float4(0.f, -1e30f, 0.f, 0.f),
-               rc = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (valid) {
-            r = rj;
-            const Rec rr = a.b.rec[(size_t)v * a.b.Rcap + r];
-            ra = rr.a;
-            rb = rr.b;
-            rc = rr.c;
-        }
-        const float mx = ra.x, my = ra.y, qa = ra.z, qb = ra.w, qc = rb.x, lo = rb.y;
-        const float cr = rb.z, cg = rb.w, cb = rc.x, w = rc.y;
-        // vertical extent of the footprint, to skip pixel groups no lane reaches
-        float ylo = 1e30f, yhi = -1e30f;
-        if (valid) {
-            const float A = -qa, B = -0.5f * qb, C = -qc;
-            const float det = A * C - B * B;
-            const float tau = (lo - kLog2AlphaMin) * 1.001f + 1e-3f;
-            if (tau > 0.f && det > 0.f) {
-                const float hy = sqrtf(tau * A / det) + 0.01f;
-                ylo = my - hy;
-                yhi = my + hy;
+        __builtin_amdgcn_wave_barrier();
+        const int gxp = (g % GX) * kGroup, gyp = (g / GX) * kGroup;
+        float dy[kGroup];
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) dy[r] = dy0 + (float)(gyp + r);
+        // columns stay a loop: unrolled, the per-column moment updates are deferred and
+        // every column's partial sums stay live
+#pragma unroll 1
+        for (int c = 0; c < kGroup; ++c) {
+            const float dx = dx0 + (float)(gxp + c);
+            const float kb = exp_col_b(qb, dx), kc = exp_col_c(qa, lo, dx);
+            float c0 = 0.f, cy = 0.f, cyy = 0.f;
+#pragma unroll
+            for (int r = 0; r < kGroup; ++r) {
+                const float e = exp_pix(qc, dy[r], kb, kc);
+                if (e >= kLog2AlphaMin) {
+                    const float4 pc = s_c[wave][r * kGroup + c];
+                    const float Bc = s_B[wave][r * kGroup + c];
+                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+                    const float kal = al < kAlphaMax ? al : 0.f;   // d alpha / de / ln 2; 0 when capped
+                    // A . c - s1 (pc.w holds -s1)
+                    const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
+                    const float aw = al * w;
+                    g_cr = fmaf(pc.x, aw, g_cr);
+                    g_cg = fmaf(pc.y, aw, g_cg);
+                    g_cb = fmaf(pc.z, aw, g_cb);
+                    g_w = fmaf(al, diff, g_w);
+                    // dL/dalpha = B / (1 - alpha) + w diff
+                    const float dLde = kal * fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                    const float ey = dLde * dy[r];
+                    c0 += dLde;
+                    cy += ey;
+                    cyy = fmaf(ey, dy[r], cyy);
+                }
             }
+            m0 += c0;
+            m_x = fmaf(dx, c0, m_x);
+            m_xx = fmaf(dx * dx, c0, m_xx);
+            m_y += cy;
+            m_xy = fmaf(dx, cy, m_xy);
+            m_yy += cyy;
         }
-        float g_mx = 0.f, g_my = 0.f, g_qa = 0.f, g_qb = 0.f, g_qc = 0.f, g_lo = 0.f;
-        float g_cr = 0.f, g_cg = 0.f, g_cb = 0.f, g_w = 0.f;
-        const size_t pb = (size_t)cam.pix_base;
-        const int cols = min(S, cam.W - tx * S);   // in-image columns of this tile
+        __builtin_amdgcn_wave_barrier();
+        if (gn < 0) break;
+        g = gn;
+    }
+    if (valid) {
+        // de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
+        // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
+        float *dst = b.sgrad + ((size_t)v * b.Acap + rj) * 10;
+        const float vals[10] = {-(2.f * qa * m_x + qb * m_y) * kLn2,
+                                -(qb * m_x + 2.f * qc * m_y) * kLn2,
+                                m_xx * kLn2,
+                                m_xy * kLn2,
+                                m_yy * kLn2,
+                                m0 * kLn2,
+                                g_cr,
+                                g_cg,
+                                g_cb,
+                                g_w};
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (vals[k] != 0.f) unsafeAtomicAdd(dst + k, vals[k]);
+    }
+}
 
-        for (int grp = 0; grp < GROUPS; ++grp) {
-            const float gy0 = (float)(ty * S + grp * ROWS) + 0.5f;
-            const float gy1 = gy0 + (float)(ROWS - 1);
-            const bool hit = (ylo <= gy1) && (yhi >= gy0);
-            if (__ballot(hit) == 0) continue;
-            // stage this group's pixel constants: lane = pixel
-            {
-                const int p = grp * 64 + lane;
-                const int x = tx * S + p % S, y = ty * S + p / S;
-                float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (x < cam.W && y < cam.H) {
-                    const size_t gp = pb + (size_t)y * cam.W + x;
-                    c0 = a.b.pixconst[2 * gp];
-                    c1 = a.b.pixconst[2 * gp + 1];
-                }
-                s_pc[wave][lane][0] = c0;
-                s_pc[wave][lane][1] = c1;
-            }
-            __builtin_amdgcn_wave_barrier();
-            // walk the group row by row; per-row terms of the exponent are hoisted, and
-            // the exponent is formed with the same operations as alpha_exponent() so that
-            // forward and backward take identical decisions for every pair
-            for (int row = 0; row < ROWS; ++row) {
-                const int y = ty * S + grp * ROWS + row;
-                if (y >= cam.H) break;
-                const float dy = ((float)y + 0.5f) - my;
-                const float qbdy = qb * dy;
-                const float cterm = fmaf(qc * dy, dy, lo);
-#pragma unroll
-                for (int col = 0; col < S; ++col) {
-                    if (col >= cols) break;
-                    const float dx = ((float)(tx * S + col) + 0.5f) - mx;
-                    const float e = fmaf(dx, fmaf(qa, dx, qbdy), cterm);
-                    if (e >= kLog2AlphaMin) {
-                        const int jj = row * S + col;
-                        const float4 c0 = s_pc[wave][jj][0];
-                        const bool capped = e > kLog2AlphaMax;
-                        const float al = capped ? kAlphaMax : __builtin_amdgcn_exp2f(e);
-                        const float diff = fmaf(c0.x, cr, fmaf(c0.y, cg, c0.z * cb)) - c0.w;
-                        const float aw = al * w;
-                        g_cr = fmaf(c0.x, aw, g_cr);
-                        g_cg = fmaf(c0.y, aw, g_cg);
-                        g_cb = fmaf(c0.z, aw, g_cb);
-                        g_w = fmaf(al, diff, g_w);
-                        if (!capped) {
-                            const float Bc = s_pc[wave][jj][1].x;
-                            // dL/dalpha = B / (1 - alpha) + w diff;  d alpha / de = alpha ln 2
-                            // (the ln 2 is applied once per work item, below)
-                            const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
-                            const float dLde = dLda * al;
-                            g_lo += dLde;
-                            const float ex = dLde * dx, ey = dLde * dy;
-                            g_qa = fmaf(ex, dx, g_qa);
-                            g_qb = fmaf(ex, dy, g_qb);
-                            g_qc = fmaf(ey, dy, g_qc);
-                            // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
-                            g_mx -= fmaf(2.f * qa, ex, qb * ey);
-                            g_my -= fmaf(qb, ex, 2.f * qc * ey);
-                        }
-                    }
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (valid) {
-            float *dst = a.b.sgrad + ((size_t)v * a.b.Acap + r) * 10;
-            const float vals[10] = {g_mx * kLn2, g_my * kLn2, g_qa * kLn2, g_qb * kLn2, g_qc * kLn2, g_lo * kLn2,
-                                    g_cr, g_cg, g_cb, g_w};
-#pragma unroll
-            for (int k = 0; k < 10; ++k)
-                if (vals[k] != 0.f) unsafeAtomicAdd(dst + k, vals[k]);
+template <int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a)
+{
+    __shared__ float4 s_c[4][64];
+    __shared__ float s_B[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
+    if (total > a.b.max_chunks) total = a.b.max_chunks;
+    const int xcd = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int q = (xcd + k) % kXcds;
+        const uint32_t q0 = (uint32_t)(((uint64_t)total * q) / kXcds);
+        const uint32_t q1 = (uint32_t)(((uint64_t)total * (q + 1)) / kXcds);
+        for (;;) {
+            uint32_t ticket = 0;
+            if (lane == 0) ticket = atomicAdd(&a.b.counters[CNT_XQUEUE + q], 1u);
+            ticket = __builtin_amdgcn_readfirstlane(ticket);
+            if (ticket >= q1 - q0) break;
+            bwd_item<S>(a.b, q0 + ticket, wave, lane, s_c, s_B);
         }
     }
 }
@@ -289,6 +357,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     constexpr int PPT = S * S / NT;
+    constexpr int RSTEP = NT / S;
     constexpr int B = 64;
     __shared__ float4 s_rec[B * 3];
     __shared__ uint32_t s_r[B];
@@ -297,26 +366,28 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
     const CamDev &cam = a.b.cams[v];
     const int lt = tile - cam.tile_base;
     const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
-    float px[PPT], py[PPT], A0[PPT], A1[PPT], A2[PPT], s1[PPT], Bc[PPT];
+    const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
+    const int col = threadIdx.x % S, row0 = threadIdx.x / S;
+    const float colf = (float)col;
+    float rowf[PPT], A0[PPT], A1[PPT], A2[PPT], ns1[PPT], Bc[PPT];
     bool in[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int li = threadIdx.x + p * NT;
-        const int x = tx * S + li % S, y = ty * S + li / S;
-        px[p] = (float)x + 0.5f;
-        py[p] = (float)y + 0.5f;
+        const int x = tx * S + col, y = ty * S + row0 + p * RSTEP;
+        rowf[p] = (float)(row0 + p * RSTEP);
         in[p] = x < cam.W && y < cam.H;
-        float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f), c1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float cB = 0.f;
         if (in[p]) {
             const size_t gp = (size_t)cam.pix_base + (size_t)y * cam.W + x;
-            c0 = a.b.pixconst[2 * gp];
-            c1 = a.b.pixconst[2 * gp + 1];
+            c0 = a.b.pixconst[gp];
+            cB = a.b.pixB[gp];
         }
         A0[p] = c0.x;
         A1[p] = c0.y;
         A2[p] = c0.z;
-        s1[p] = c0.w;
-        Bc[p] = c1.x;
+        ns1[p] = c0.w;
+        Bc[p] = cB;
     }
     const uint64_t cap = (uint64_t)a.b.pair_cap;
     const uint64_t off = a.b.tile_off[tile];
@@ -330,7 +401,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
             const uint32_t ri = a.b.entries[off + base + j];
             const bool ok = ri < a.b.Acap;
             const Rec r = ok ? recv[ri] : Rec{{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-            s_rec[3 * j] = r.a;
+            s_rec[3 * j] = make_float4(x0 - r.a.x, y0 - r.a.y, r.a.z, r.a.w);
             s_rec[3 * j + 1] = r.b;
             s_rec[3 * j + 2] = r.c;
             s_r[j] = ok ? ri : 0u;
@@ -339,22 +410,23 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
             float *dst = a.b.sgrad + ((size_t)v * a.b.Acap + s_r[j]) * 10;
+            const float dx = ra.x + colf;
+            const float kb = exp_col_b(ra.w, dx), kc = exp_col_c(ra.z, rb.y, dx);
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
                 if (!in[p]) continue;
-                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
-                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
+                const float dy = ra.y + rowf[p];
+                const float e = exp_pix(rb.x, dy, kb, kc);
                 if (e < kLog2AlphaMin) continue;
-                const bool capped = e > kLog2AlphaMax;
-                const float al = capped ? kAlphaMax : __builtin_amdgcn_exp2f(e);
+                const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
                 const float w = rc.y;
-                const float diff = fmaf(A0[p], rb.z, fmaf(A1[p], rb.w, A2[p] * rc.x)) - s1[p];
+                const float diff = fmaf(A0[p], rb.z, fmaf(A1[p], rb.w, fmaf(A2[p], rc.x, ns1[p])));
                 const float aw = al * w;
                 unsafeAtomicAdd(dst + 6, A0[p] * aw);
                 unsafeAtomicAdd(dst + 7, A1[p] * aw);
                 unsafeAtomicAdd(dst + 8, A2[p] * aw);
                 unsafeAtomicAdd(dst + 9, al * diff);
-                if (!capped) {
+                if (al < kAlphaMax) {
                     const float dLde = fmaf(w, diff, Bc[p] * __builtin_amdgcn_rcpf(1.f - al)) * al * kLn2;
                     const float ex = dLde * dx, ey = dLde * dy;
                     unsafeAtomicAdd(dst + 0, -fmaf(2.f * ra.z, ex, ra.w * ey));
@@ -369,12 +441,16 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
     }
 }
 
+// Persistent grid of the per-splat backward: 8 workgroups of 4 waves per CU of the
+// largest device (256 CUs); surplus workgroups find the queues drained and exit.
+constexpr unsigned kBwdBlocks = 2048;
+
 bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s)
 {
     (void)rl;
     BwdArgs a{b};
+    if (b.T == 0) return true;
     if (b.bwd_mode == OIT_BWD_PER_PIXEL) {
-        if (b.T == 0) return true;
         switch (b.tile) {
         case 8: hipLaunchKernelGGL(k_raster_bwd_pixel<8>, dim3(b.T), dim3(64), 0, s, a); return true;
         case 16: hipLaunchKernelGGL(k_raster_bwd_pixel<16>, dim3(b.T), dim3(256), 0, s, a); return true;
@@ -382,7 +458,8 @@ bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s)
         default: return false;
         }
     }
-    const dim3 grid(1024), block(256);
+    hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((b.T + 255) / 256)), dim3(256), 0, s, b);
+    const dim3 grid(kBwdBlocks), block(256);
     switch (b.tile) {
     case 8: hipLaunchKernelGGL(k_raster_bwd<8>, grid, block, 0, s, a); return true;
     case 16: hipLaunchKernelGGL(k_raster_bwd<16>, grid, block, 0, s, a); return true;

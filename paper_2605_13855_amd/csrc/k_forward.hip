@@ -311,7 +311,8 @@ void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s)
 // ---------------------------------------------------------------------------------
 // raster forward: one workgroup per tile (all views of the batch in one launch).
 // Records of the tile's entries are staged through LDS in batches; every thread
-// blends them into its pixels in list order (no depth order).
+// blends them into its pixels in list order (no depth order).  A thread's pixels
+// share one column, so the per-column exponent terms are formed once per record.
 // ---------------------------------------------------------------------------------
 struct FwdArgs {
     Buffers b;
@@ -324,11 +325,21 @@ struct FwdArgs {
 // stands in for any tile-list entry outside its class's record range.
 __device__ const Rec kNoRec = {{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 
+// Stage record r for a tile whose first pixel centre is (x0, y0): the mean is
+// replaced by the offsets x0 - mx, y0 - my of the exponent form.
+__device__ __forceinline__ void stage_rec(float4 *dst, const Rec &r, float x0, float y0)
+{
+    dst[0] = make_float4(x0 - r.a.x, y0 - r.a.y, r.a.z, r.a.w);
+    dst[1] = r.b;
+    dst[2] = r.c;
+}
+
 template <int S, int BATCH>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArgs a)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     constexpr int PPT = S * S / NT;
+    constexpr int RSTEP = NT / S;   // rows between one thread's pixels
     __shared__ float4 s_rec[BATCH * 3];
 
     const int tile = blockIdx.x;
@@ -336,23 +347,22 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     const CamDev &cam = a.b.cams[v];
     const int lt = tile - cam.tile_base;
     const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+    const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
+    const int col = threadIdx.x % S, row0 = threadIdx.x / S;
+    const float colf = (float)col;
+    const bool col_in = tx * S + col < cam.W;
+    const size_t HW = (size_t)cam.W * cam.H;
+    const size_t pb = (size_t)cam.pix_base;
 
-    float px[PPT], py[PPT];
-    float P[PPT][3], Q[PPT], T[PPT];
-    uint32_t npair[PPT];   // contributing active pairs per pixel (throughput counter)
-    float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT];
+    float rowf[PPT];
+    bool in[PPT];
+    uint64_t inmask[PPT];   // lanes whose pixel p lies in the image
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int li = threadIdx.x + p * NT;
-        px[p] = (float)(tx * S + li % S) + 0.5f;
-        py[p] = (float)(ty * S + li / S) + 0.5f;
-        P[p][0] = P[p][1] = P[p][2] = 0.f;
-        Q[p] = 0.f;
-        T[p] = 1.f;
-        dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
-        dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
-        dQ0[p] = dQ1[p] = dL[p] = 0.f;
-        npair[p] = 0;
+        const int row = row0 + p * RSTEP;
+        rowf[p] = (float)row;
+        in[p] = col_in && ty * S + row < cam.H;
+        inmask[p] = __ballot(in[p]);
     }
 
     const uint64_t cap = (uint64_t)a.b.pair_cap;
@@ -362,25 +372,89 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     if (off + na + nd > cap) nd = off + na < cap ? cap - off - na : 0;
     const Rec *recv = a.b.rec + (size_t)v * a.b.Rcap;
 
+    // label changes first: BAU accumulators (sign-weighted, sigma-free), folded into
+    // the pre-rendered buffer before the active pass so that they are not live there
+    if (nd) {
+        float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
+            dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
+            dQ0[p] = dQ1[p] = dL[p] = 0.f;
+        }
+        for (uint64_t base = 0; base < nd; base += BATCH) {
+            const int cnt = (int)(nd - base < (uint64_t)BATCH ? nd - base : (uint64_t)BATCH);
+            __syncthreads();
+            for (int j = threadIdx.x; j < cnt; j += NT) {
+                const uint32_t ri = a.b.entries[off + na + base + j];
+                stage_rec(&s_rec[3 * j], (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec, x0, y0);
+            }
+            __syncthreads();
+            for (int j = 0; j < cnt; ++j) {
+                const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+                const float dx = ra.x + colf;
+                const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
+                    if (e >= kLog2AlphaMin) {
+                        const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+                        const float sav = rc.w * al * rc.y;       // sign * alpha * v
+                        const float savd = sav * rc.z;            // ... * d
+                        dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
+                        dP0[p][1] = fmaf(rb.w, sav, dP0[p][1]);
+                        dP0[p][2] = fmaf(rc.x, sav, dP0[p][2]);
+                        dP1[p][0] = fmaf(rb.z, savd, dP1[p][0]);
+                        dP1[p][1] = fmaf(rb.w, savd, dP1[p][1]);
+                        dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
+                        dQ0[p] += sav;
+                        dQ1[p] += savd;
+                        dL[p] = fmaf(rc.w, __builtin_amdgcn_logf(1.f - al) * kLn2, dL[p]);
+                    }
+                }
+            }
+        }
+        if (a.pre) {
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                if (!in[p]) continue;
+                const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
+                float *pr = a.pre + 9 * pb + pix;
+                const float add[9] = {dP0[p][0], dP0[p][1], dP0[p][2], dP1[p][0], dP1[p][1],
+                                      dP1[p][2], dQ0[p],    dQ1[p],    dL[p]};
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pr[k * HW] += add[k];
+            }
+        }
+    }
+
     // active entries: BAN accumulators
+    float P[PPT][3], Q[PPT], T[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        P[p][0] = P[p][1] = P[p][2] = 0.f;
+        Q[p] = 0.f;
+        T[p] = 1.f;
+    }
+    unsigned long long npair = 0;   // contributing in-image active pairs of this wave (counter)
     for (uint64_t base = 0; base < na; base += BATCH) {
         const int cnt = (int)(na - base < (uint64_t)BATCH ? na - base : (uint64_t)BATCH);
         __syncthreads();
         for (int j = threadIdx.x; j < cnt; j += NT) {
             const uint32_t ri = a.b.entries[off + base + j];
-            const Rec r = ri < a.b.Acap ? recv[ri] : kNoRec;
-            s_rec[3 * j] = r.a;
-            s_rec[3 * j + 1] = r.b;
-            s_rec[3 * j + 2] = r.c;
+            stage_rec(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+            const float dx = ra.x + colf;
+            const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
-                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
-                if (e >= kLog2AlphaMin) {
+                const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
+                const bool hit = e >= kLog2AlphaMin;
+                npair += (unsigned long long)__builtin_popcountll(__ballot(hit) & inmask[p]);
+                if (hit) {
                     const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
                     const float aw = al * rc.y;
                     P[p][0] = fmaf(rb.z, aw, P[p][0]);
@@ -388,42 +462,6 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                     P[p][2] = fmaf(rc.x, aw, P[p][2]);
                     Q[p] += aw;
                     T[p] *= 1.f - al;
-                    ++npair[p];
-                }
-            }
-        }
-    }
-    // label changes: BAU accumulators (sign-weighted, sigma-free)
-    for (uint64_t base = 0; base < nd; base += BATCH) {
-        const int cnt = (int)(nd - base < (uint64_t)BATCH ? nd - base : (uint64_t)BATCH);
-        __syncthreads();
-        for (int j = threadIdx.x; j < cnt; j += NT) {
-            const uint32_t ri = a.b.entries[off + na + base + j];
-            const Rec r = (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec;
-            s_rec[3 * j] = r.a;
-            s_rec[3 * j + 1] = r.b;
-            s_rec[3 * j + 2] = r.c;
-        }
-        __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
-            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
-#pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                const float dx = px[p] - ra.x, dy = py[p] - ra.y;
-                const float e = alpha_exponent(rb.y, ra.z, ra.w, rb.x, dx, dy);
-                if (e >= kLog2AlphaMin) {
-                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
-                    const float sav = rc.w * al * rc.y;       // sign * alpha * v
-                    const float savd = sav * rc.z;            // ... * d
-                    dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
-                    dP0[p][1] = fmaf(rb.w, sav, dP0[p][1]);
-                    dP0[p][2] = fmaf(rc.x, sav, dP0[p][2]);
-                    dP1[p][0] = fmaf(rb.z, savd, dP1[p][0]);
-                    dP1[p][1] = fmaf(rb.w, savd, dP1[p][1]);
-                    dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
-                    dQ0[p] += sav;
-                    dQ1[p] += savd;
-                    dL[p] = fmaf(rc.w, __builtin_amdgcn_logf(1.f - al) * kLn2, dL[p]);
                 }
             }
         }
@@ -431,13 +469,8 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
 
     // throughput counters: contributing active pairs and evaluated (in-image) pairs
     {
-        unsigned long long c = 0;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p)
-            if ((int)px[p] < cam.W && (int)py[p] < cam.H) c += npair[p];
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
         __shared__ unsigned long long s_cnt[NT / 64 > 0 ? NT / 64 : 1];
-        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = c;
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = npair;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long t = 0;
@@ -450,33 +483,17 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
 
     const float sigma = *a.sigma;
     const float isig = 1.f / sigma;
-    const size_t HW = (size_t)cam.W * cam.H;
-    const size_t pb = (size_t)cam.pix_base;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int x = (int)px[p], y = (int)py[p];
-        if (x >= cam.W || y >= cam.H) continue;
-        const size_t pix = (size_t)y * cam.W + x;
+        if (!in[p]) continue;
+        const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
         float Pt[3] = {P[p][0], P[p][1], P[p][2]};
         float Qt = Q[p], Tt = T[p];
         if (a.pre) {
-            float *pr = a.pre + 9 * pb;
+            const float *pr = a.pre + 9 * pb + pix;
             float pv[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW + pix];
-            if (nd) {
-                pv[0] += dP0[p][0];
-                pv[1] += dP0[p][1];
-                pv[2] += dP0[p][2];
-                pv[3] += dP1[p][0];
-                pv[4] += dP1[p][1];
-                pv[5] += dP1[p][2];
-                pv[6] += dQ0[p];
-                pv[7] += dQ1[p];
-                pv[8] += dL[p];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) pr[k * HW + pix] = pv[k];
-            }
+            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) Pt[ch] += pv[ch] - pv[3 + ch] * isig;
             Qt += pv[6] - pv[7] * isig;

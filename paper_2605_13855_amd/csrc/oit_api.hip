@@ -47,7 +47,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
-    size_t status, cams, counters, tiles, tile_off, chunk_off, entries, rec, rect, sgrad, pixconst, total;
+    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, rec, rect, sgrad, pixconst,
+        pixB, total;
+    uint32_t max_chunks;
     int T;
     int64_t total_px, Acap, Rcap;
     CamDev cams_host[kMaxViews];
@@ -145,11 +147,16 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.tiles = o; o = align256(o + 4 * 4 * (size_t)p.T);
     p.tile_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
     p.chunk_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
+    // every tile adds at most one partial chunk to the pair capacity's full ones
+    const uint64_t mc = (uint64_t)tu->pair_capacity / kBwdLanes + (uint64_t)p.T + 1;
+    p.max_chunks = (uint32_t)(mc < 0xffffffffull ? mc : 0xffffffffull);
+    p.chunk_tile = o; o = align256(o + 4 * (size_t)p.max_chunks);
     p.entries = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
     p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
     p.rect = o; o = align256(o + sizeof(short4) * (size_t)n_views * p.Rcap);
     p.sgrad = o; o = align256(o + 4 * 10 * (size_t)n_views * p.Acap);
-    p.pixconst = o; o = align256(o + 32 * (size_t)p.total_px);
+    p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
+    p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
     p.total = o;
     return OIT_OK;
 }
@@ -167,11 +174,14 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.fill_d = b.fill_a + p.T;
     b.tile_off = (uint32_t *)(w + p.tile_off);
     b.chunk_off = (uint32_t *)(w + p.chunk_off);
+    b.chunk_tile = (uint32_t *)(w + p.chunk_tile);
+    b.max_chunks = p.max_chunks;
     b.entries = (uint32_t *)(w + p.entries);
     b.rec = (Rec *)(w + p.rec);
     b.rect = (short4 *)(w + p.rect);
     b.sgrad = (float *)(w + p.sgrad);
     b.pixconst = (float4 *)(w + p.pixconst);
+    b.pixB = (float *)(w + p.pixB);
     b.n_views = n_views;
     b.T = p.T;
     b.tile = tu->tile;
@@ -418,7 +428,7 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
                      grads->stride};
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_f32(b.sgrad, 10 * (size_t)n_views * p.Acap, 0.f, s);
-    fill_u32(b.counters + CNT_BWD_WORK, 1, 0u, s);
+    fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
     fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
     if (g_timing_on) (void)hipEventRecord(g_ev[2], s);

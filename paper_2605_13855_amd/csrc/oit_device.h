@@ -206,10 +206,18 @@ __device__ __forceinline__ bool geometry(const CamDev &cam, const float mu[3], c
     return true;
 }
 
-// Opacity exponent: returns e with alpha = 2^e (see the file comment).
-__device__ __forceinline__ float alpha_exponent(float lo, float qa, float qb, float qc, float dx, float dy)
+// Opacity exponent e (alpha = 2^e, see the file comment) at a pixel of a tile.  Both
+// raster passes form it with the same float operations, so they take identical
+// per-pair decisions:
+//   dx = (x0 - mx) + col,  dy = (y0 - my) + row     (x0, y0: centre of the tile's
+//                                                    first pixel; col, row: offsets)
+//   e  = fma(dy, fma(qc, dy, qb dx), fma(qa dx, dx, lo)).
+// The two per-column terms are exp_col_b and exp_col_c; a pixel adds two FMAs.
+__device__ __forceinline__ float exp_col_b(float qb, float dx) { return qb * dx; }
+__device__ __forceinline__ float exp_col_c(float qa, float lo, float dx) { return fmaf(qa * dx, dx, lo); }
+__device__ __forceinline__ float exp_pix(float qc, float dy, float colb, float colc)
 {
-    return fmaf(dx, fmaf(qa, dx, qb * dy), fmaf(qc * dy, dy, lo));
+    return fmaf(dy, fmaf(qc, dy, colb), colc);
 }
 
 // Conservative test: does the ellipse {m(d) <= tau}, m = A dx^2 + 2B dx dy + C dy^2,

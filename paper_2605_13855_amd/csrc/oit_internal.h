@@ -15,7 +15,9 @@ constexpr int kScanThreads = 1024;
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
-enum { CNT_BWD_WORK = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_SLOTS = 16 };
+// CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue counters
+enum { CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8, CNT_SLOTS = 16 };
+constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
 struct SplatPtrs {
     const float *mean, *log_scale, *quat, *logit, *sh, *vsh;
@@ -45,11 +47,14 @@ struct Buffers {
     uint32_t *counters;
     uint32_t *cnt_a, *cnt_d, *fill_a, *fill_d;  // [T]
     uint32_t *tile_off, *chunk_off;             // [T + 1]
+    uint32_t *chunk_tile;                       // [max_chunks] tile of each backward work item
     uint32_t *entries;                          // [pair_cap]
     Rec *rec;                                   // [V][Rcap]
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
     float *sgrad;                               // [V][Acap][10]
-    float4 *pixconst;                           // [total_px][2]
+    float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
+    float *pixB;                                // [total_px] B
+    uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
     int64_t total_px, pair_cap;
     int64_t Acap, Rcap;                         // record stride: Rcap per view
