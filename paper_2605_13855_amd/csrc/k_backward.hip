@@ -481,238 +481,324 @@ struct PreBwdArgs {
     double *grad_sigma;
     float *score;
     float eps[6];
+    int vlanes;   // lanes per row: the view count rounded up to a power of two (<= 64)
 };
 
-__global__ __launch_bounds__(256) void k_preprocess_bwd(PreBwdArgs a)
+// Per-view share of one active row's parameter gradient: everything the views sum.
+struct ViewPart {
+    float g_mu[3];   // mean (geometry and the viewing direction)
+    float G6[6];     // 3D covariance (upper triangle of the symmetric gradient)
+    float g_lo;      // log2 opacity
+    float gcm[3];    // colour gradient where the channel is not clamped
+    float gvm;       // view-weight gradient where v(r) is not clamped and d < sigma
+    float Y[16];     // SH basis at the viewing direction
+    double gsig;     // sigma
+};
+
+// Chain rule of one view, from the record's 10 screen-space partials to the splat's
+// parameters (Sec. 3.1 model; the inverse of the forward projection step by step).
+__device__ void view_partials(const PreBwdArgs &a, int64_t t, int64_t id, int v, const float mu[3],
+                              const float S6[6], float sigma, ViewPart &o)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = a.sp.n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.g_mu[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o.G6[k] = 0.f;
+    o.g_lo = 0.f;
+    o.gcm[0] = o.gcm[1] = o.gcm[2] = 0.f;
+    o.gvm = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o.Y[k] = 0.f;
+    o.gsig = 0.0;
+
+    const float *sg = a.b.sgrad + ((size_t)v * a.b.Acap + t) * 10;
+    float gs[10];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        gs[k] = sg[k];
+        any |= gs[k] != 0.f;
+    }
+    if (!any) return;
+    const CamDev &cam = a.b.cams[v];
+    Geo g;
+    if (!geometry(cam, mu, S6, g)) return;
+    const float tz = g.tc[2], itz = 1.f / tz;
+    float g_tc[3] = {0.f, 0.f, 0.f};
+    o.g_lo = gs[5];
+
+    // appearance: colour and view weight at the viewing direction
+    float u[3] = {mu[0] - cam.cc[0], mu[1] - cam.cc[1], mu[2] - cam.cc[2]};
+    const float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float idist = 1.f / dist;
+    const float dir[3] = {u[0] * idist, u[1] * idist, u[2] * idist};
+    sh_eval(dir[0], dir[1], dir[2], o.Y);
+    float gY[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gY[k] = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float raw = kColorOffset;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) raw += o.Y[k] * a.sp.sh[(3 * k + ch) * n + id];
+        if (raw > 0.f) {
+            const float gc = gs[6 + ch];
+            o.gcm[ch] = gc;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) gY[k] = fmaf(gc, a.sp.sh[(3 * k + ch) * n + id], gY[k]);
+        }
+    }
+    {
+        float raw = kColorOffset;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) raw += o.Y[k] * a.sp.vsh[k * n + id];
+        const float vv = fmaxf(raw, 0.f);
+        const float gw = gs[9];
+        if (tz < sigma) {
+            const float gv = gw * (1.f - tz / sigma);
+            g_tc[2] += -gw * vv / sigma;
+            o.gsig = (double)gw * (double)vv * (double)tz / ((double)sigma * (double)sigma);
+            if (raw > 0.f) {
+                o.gvm = gv;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) gY[k] = fmaf(gv, a.sp.vsh[k * n + id], gY[k]);
+            }
+        }
+    }
+    float gdir[3];
+    sh_vjp(dir[0], dir[1], dir[2], gY, gdir);
+    {
+        const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o.g_mu[k] += (gdir[k] - dir[k] * dd) * idist;
+    }
+
+    // conic (scaled): qa = h A, qb = 2 h B, qc = h C with h = -log2(e)/2
+    const float h = -0.5f * kLog2e;
+    const float gA = h * gs[2], gB = 2.f * h * gs[3], gC = h * gs[4];
+    // conic = cov^-1: G_cov = -K G K with G = [[gA, gB/2], [gB/2, gC]]
+    const float A = g.con_a, Bk = g.con_b, C = g.con_c, hb = 0.5f * gB;
+    const float ga = -(A * A * gA + 2.f * A * Bk * hb + Bk * Bk * gC);
+    const float gb = -2.f * (A * Bk * gA + (Bk * Bk + A * C) * hb + Bk * C * gC);
+    const float gcc = -(Bk * Bk * gA + 2.f * Bk * C * hb + C * C * gC);
+    // cov = T Sigma T^T + 0.3 I
+    const float Sg[9] = {S6[0], S6[1], S6[2], S6[1], S6[3], S6[4], S6[2], S6[4], S6[5]};
+    float Vm[6];
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+            Vm[3 * aa + bb] = g.T[3 * aa] * Sg[bb] + g.T[3 * aa + 1] * Sg[3 + bb] + g.T[3 * aa + 2] * Sg[6 + bb];
+    const float hgb = 0.5f * gb;
+    float gT[6];
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+        gT[bb] = 2.f * (ga * Vm[bb] + hgb * Vm[3 + bb]);
+        gT[3 + bb] = 2.f * (hgb * Vm[bb] + gcc * Vm[3 + bb]);
+    }
+    // G_Sigma (full, symmetric) = T^T Gc T
+    {
+        const float *T0 = g.T, *T1 = g.T + 3;
+        const int ks[6] = {0, 0, 0, 1, 1, 2}, ls[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int k = ks[e], l = ls[e];
+            o.G6[e] = ga * T0[k] * T0[l] + hgb * (T0[k] * T1[l] + T1[k] * T0[l]) + gcc * T1[k] * T1[l];
+        }
+    }
+    // T = J W
+    const float gJ00 = gT[0] * cam.R[0] + gT[1] * cam.R[1] + gT[2] * cam.R[2];
+    const float gJ02 = gT[0] * cam.R[6] + gT[1] * cam.R[7] + gT[2] * cam.R[8];
+    const float gJ11 = gT[3] * cam.R[3] + gT[4] * cam.R[4] + gT[5] * cam.R[5];
+    const float gJ12 = gT[3] * cam.R[6] + gT[4] * cam.R[7] + gT[5] * cam.R[8];
+    g_tc[2] += -gJ00 * g.J00 * itz - gJ11 * g.J11 * itz;
+    if (g.clamp_x == 0) {
+        g_tc[0] += gJ02 * (-cam.fx * itz * itz);
+        g_tc[2] += gJ02 * (-2.f * g.J02 * itz);
+    } else {
+        g_tc[2] += gJ02 * (-g.J02 * itz);
+    }
+    if (g.clamp_y == 0) {
+        g_tc[1] += gJ12 * (-cam.fy * itz * itz);
+        g_tc[2] += gJ12 * (-2.f * g.J12 * itz);
+    } else {
+        g_tc[2] += gJ12 * (-g.J12 * itz);
+    }
+    // mean' = (fx tx / tz + cx, fy ty / tz + cy)
+    g_tc[0] += gs[0] * cam.fx * itz;
+    g_tc[1] += gs[1] * cam.fy * itz;
+    g_tc[2] += -(gs[0] * cam.fx * g.tc[0] + gs[1] * cam.fy * g.tc[1]) * itz * itz;
+    // tc = R mu + t
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.g_mu[k] += cam.R[k] * g_tc[0] + cam.R[3 + k] * g_tc[1] + cam.R[6 + k] * g_tc[2];
+}
+
+// ---------------------------------------------------------------------------------
+// preprocess backward: a group of `vlanes` lanes per active row, one lane per view.
+// Each lane forms its view's share of the parameter gradient (view_partials); the
+// shares meet in LDS, where the row's lanes sum them: lane 0 finishes the geometric
+// chain (covariance -> log-scales and quaternion, opacity), every lane a quarter of
+// the 64 SH outputs.  Also the activeness score (Sec. 4.1) and dL/dsigma (FP64).
+// ---------------------------------------------------------------------------------
+constexpr int kPbThreads = 256;
+constexpr unsigned kPbBlocks = 1024;
+
+__global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
+{
+    __shared__ float s_geo[kPbThreads][10];   // g_mu, G6, g_lo
+    __shared__ float s_app[kPbThreads][20];   // gcm (3), gvm, Y (16)
+    __shared__ float s_n2[kPbThreads][2];     // partial squared norms of the sh / vsh outputs
+    const int P = a.vlanes, V = a.b.n_views;
+    const int rows_per_block = kPbThreads / P;
+    const int lr = threadIdx.x / P, vl = threadIdx.x % P;
+    const int64_t n = a.sp.n;
+    const int64_t st = a.g.stride;
+    int64_t na = a.rl.n_active ? (int64_t)*a.rl.n_active : a.rl.n_active_host;
+    na = na < 0 ? 0 : (na > a.rl.Acap ? a.rl.Acap : na);
+    const float sigma = *a.sigma;
     double gsig = 0.0;
-    const int64_t na = a.rl.n_active ? (int64_t)*a.rl.n_active : a.rl.n_active_host;
-    if (t < a.rl.Acap && t < na) {
-        const int64_t id = a.rl.active_idx ? (int64_t)a.rl.active_idx[t] : t;
-        const int64_t n = a.sp.n;
-        const float sigma = *a.sigma;
-        float mu[3], s[3], q[4];
+
+    for (int64_t base = (int64_t)blockIdx.x * rows_per_block; base < na;
+         base += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t t = base + lr;
+        const bool row_ok = t < na;
+        const int64_t id = row_ok ? (a.rl.active_idx ? (int64_t)a.rl.active_idx[t] : t) : 0;
+        float mu[3], s3[3], qn[4], Rq[9], S6[6], qi = 1.f;
+        if (row_ok) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            mu[k] = a.sp.mean[k * n + id];
-            s[k] = expf(a.sp.log_scale[k * n + id]);
+            for (int k = 0; k < 3; ++k) {
+                mu[k] = a.sp.mean[k * n + id];
+                s3[k] = expf(a.sp.log_scale[k * n + id]);
+            }
+            float q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[k * n + id];
+            qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) qn[k] = q[k] * qi;
+            quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
+            cov3d(Rq, s3, S6);
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[k * n + id];
-        const float qlen = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        const float qi = 1.f / qlen;
-        const float qn[4] = {q[0] * qi, q[1] * qi, q[2] * qi, q[3] * qi};
-        float Rq[9], S6[6];
-        quat_rot(qn[0], qn[1], qn[2], qn[3], Rq);
-        cov3d(Rq, s, S6);
-        const float lg = a.sp.logit[id];
-        const float o = 1.f / (1.f + expf(-lg));
-
-        float g_mu[3] = {0.f, 0.f, 0.f};
-        float G6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        float g_sh[48], g_vsh[16];
-#pragma unroll
-        for (int k = 0; k < 48; ++k) g_sh[k] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) g_vsh[k] = 0.f;
-        float g_lo = 0.f;
-
-        for (int v = 0; v < a.b.n_views; ++v) {
-            const float *sg = a.b.sgrad + ((size_t)v * a.b.Acap + t) * 10;
-            float gs[10];
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                gs[k] = sg[k];
-                any |= gs[k] != 0.f;
-            }
-            if (!any) continue;
-            const CamDev &cam = a.b.cams[v];
-            Geo g;
-            if (!geometry(cam, mu, S6, g)) continue;
-            const float tz = g.tc[2], itz = 1.f / tz;
-            float g_tc[3] = {0.f, 0.f, 0.f};
-            g_lo += gs[5];
-
-            // appearance: colour and view weight at the viewing direction
-            float u[3] = {mu[0] - cam.cc[0], mu[1] - cam.cc[1], mu[2] - cam.cc[2]};
-            const float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            const float idist = 1.f / dist;
-            const float dir[3] = {u[0] * idist, u[1] * idist, u[2] * idist};
-            float Y[16];
-            sh_eval(dir[0], dir[1], dir[2], Y);
-            float gY[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) gY[k] = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float raw = kColorOffset;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) raw += Y[k] * a.sp.sh[(3 * k + ch) * n + id];
-                if (raw > 0.f) {
-                    const float gc = gs[6 + ch];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) {
-                        g_sh[3 * k + ch] = fmaf(gc, Y[k], g_sh[3 * k + ch]);
-                        gY[k] = fmaf(gc, a.sp.sh[(3 * k + ch) * n + id], gY[k]);
-                    }
-                }
-            }
-            {
-                float raw = kColorOffset;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) raw += Y[k] * a.sp.vsh[k * n + id];
-                const float vv = fmaxf(raw, 0.f);
-                const float gw = gs[9];
-                if (tz < sigma) {
-                    const float gv = gw * (1.f - tz / sigma);
-                    g_tc[2] += -gw * vv / sigma;
-                    gsig += (double)gw * (double)vv * (double)tz / ((double)sigma * (double)sigma);
-                    if (raw > 0.f) {
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) {
-                            g_vsh[k] = fmaf(gv, Y[k], g_vsh[k]);
-                            gY[k] = fmaf(gv, a.sp.vsh[k * n + id], gY[k]);
-                        }
-                    }
-                }
-            }
-            float gdir[3];
-            sh_vjp(dir[0], dir[1], dir[2], gY, gdir);
-            {
-                const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) g_mu[k] += (gdir[k] - dir[k] * dd) * idist;
-            }
-
-            // conic (scaled): qa = h A, qb = 2 h B, qc = h C with h = -log2(e)/2
-            const float h = -0.5f * kLog2e;
-            const float gA = h * gs[2], gB = 2.f * h * gs[3], gC = h * gs[4];
-            // conic = cov^-1: G_cov = -K G K with G = [[gA, gB/2], [gB/2, gC]]
-            const float A = g.con_a, Bk = g.con_b, C = g.con_c, hb = 0.5f * gB;
-            const float ga = -(A * A * gA + 2.f * A * Bk * hb + Bk * Bk * gC);
-            const float gb = -2.f * (A * Bk * gA + (Bk * Bk + A * C) * hb + Bk * C * gC);
-            const float gcc = -(Bk * Bk * gA + 2.f * Bk * C * hb + C * C * gC);
-            // cov = T Sigma T^T + 0.3 I
-            const float Sg[9] = {S6[0], S6[1], S6[2], S6[1], S6[3], S6[4], S6[2], S6[4], S6[5]};
-            float V[6];
-#pragma unroll
-            for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
-                    V[3 * aa + bb] = g.T[3 * aa] * Sg[bb] + g.T[3 * aa + 1] * Sg[3 + bb] + g.T[3 * aa + 2] * Sg[6 + bb];
-            const float hgb = 0.5f * gb;
-            float gT[6];
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                gT[bb] = 2.f * (ga * V[bb] + hgb * V[3 + bb]);
-                gT[3 + bb] = 2.f * (hgb * V[bb] + gcc * V[3 + bb]);
-            }
-            // G_Sigma (full, symmetric) = T^T Gc T
-            {
-                const float *T0 = g.T, *T1 = g.T + 3;
-                const int ks[6] = {0, 0, 0, 1, 1, 2}, ls[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const int k = ks[e], l = ls[e];
-                    G6[e] += ga * T0[k] * T0[l] + hgb * (T0[k] * T1[l] + T1[k] * T0[l]) + gcc * T1[k] * T1[l];
-                }
-            }
-            // T = J W
-            const float gJ00 = gT[0] * cam.R[0] + gT[1] * cam.R[1] + gT[2] * cam.R[2];
-            const float gJ02 = gT[0] * cam.R[6] + gT[1] * cam.R[7] + gT[2] * cam.R[8];
-            const float gJ11 = gT[3] * cam.R[3] + gT[4] * cam.R[4] + gT[5] * cam.R[5];
-            const float gJ12 = gT[3] * cam.R[6] + gT[4] * cam.R[7] + gT[5] * cam.R[8];
-            g_tc[2] += -gJ00 * g.J00 * itz - gJ11 * g.J11 * itz;
-            if (g.clamp_x == 0) {
-                g_tc[0] += gJ02 * (-cam.fx * itz * itz);
-                g_tc[2] += gJ02 * (-2.f * g.J02 * itz);
+        {
+            ViewPart o;
+            if (row_ok && vl < V) {
+                view_partials(a, t, id, vl, mu, S6, sigma, o);
             } else {
-                g_tc[2] += gJ02 * (-g.J02 * itz);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) o.g_mu[k] = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) o.G6[k] = 0.f;
+                o.g_lo = 0.f;
+                o.gcm[0] = o.gcm[1] = o.gcm[2] = 0.f;
+                o.gvm = 0.f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) o.Y[k] = 0.f;
+                o.gsig = 0.0;
             }
-            if (g.clamp_y == 0) {
-                g_tc[1] += gJ12 * (-cam.fy * itz * itz);
-                g_tc[2] += gJ12 * (-2.f * g.J12 * itz);
+            gsig += o.gsig;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s_geo[threadIdx.x][k] = o.g_mu[k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s_geo[threadIdx.x][3 + k] = o.G6[k];
+            s_geo[threadIdx.x][9] = o.g_lo;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s_app[threadIdx.x][k] = o.gcm[k];
+            s_app[threadIdx.x][3] = o.gvm;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s_app[threadIdx.x][4 + k] = o.Y[k];
+        }
+        __syncthreads();
+        const int g0 = lr * P;   // first lane of this row's group
+        // SH outputs: j < 48 -> sh[j] (basis j / 3, channel j % 3); j >= 48 -> vsh[j - 48]
+        float nsh = 0.f, nvsh = 0.f;
+        for (int j = vl; j < 64; j += P) {
+            float acc = 0.f;
+            if (j < 48) {
+                const int k = j / 3, ch = j % 3;
+                for (int u = 0; u < V; ++u) acc = fmaf(s_app[g0 + u][ch], s_app[g0 + u][4 + k], acc);
+                if (row_ok) a.g.sh[j * st + t] = acc;
+                nsh += acc * acc;
             } else {
-                g_tc[2] += gJ12 * (-g.J12 * itz);
+                const int k = j - 48;
+                for (int u = 0; u < V; ++u) acc = fmaf(s_app[g0 + u][3], s_app[g0 + u][4 + k], acc);
+                if (row_ok) a.g.vsh[k * st + t] = acc;
+                nvsh += acc * acc;
             }
-            // mean' = (fx tx / tz + cx, fy ty / tz + cy)
-            g_tc[0] += gs[0] * cam.fx * itz;
-            g_tc[1] += gs[1] * cam.fy * itz;
-            g_tc[2] += -(gs[0] * cam.fx * g.tc[0] + gs[1] * cam.fy * g.tc[1]) * itz * itz;
-            // tc = R mu + t
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                g_mu[k] += cam.R[k] * g_tc[0] + cam.R[3 + k] * g_tc[1] + cam.R[6 + k] * g_tc[2];
         }
-
-        // Sigma = M M^T, M = Rq diag(s):  dL/dM = 2 G M
-        const float Gf[9] = {G6[0], G6[1], G6[2], G6[1], G6[3], G6[4], G6[2], G6[4], G6[5]};
-        float gRq[9], g_ls[3];
+        s_n2[threadIdx.x][0] = nsh;
+        s_n2[threadIdx.x][1] = nvsh;
+        __syncthreads();
+        if (row_ok && vl == 0) {
+            float g_mu[3] = {0.f, 0.f, 0.f}, G6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, g_lo = 0.f;
+            float n2[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < V; ++u) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            float gsj = 0.f;
+                for (int k = 0; k < 3; ++k) g_mu[k] += s_geo[g0 + u][k];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                float gm = 0.f;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) gm += Gf[3 * i + k] * Rq[3 * k + j] * s[j];
-                gm *= 2.f;
-                gsj += gm * Rq[3 * i + j];
-                gRq[3 * i + j] = gm * s[j];
+                for (int k = 0; k < 6; ++k) G6[k] += s_geo[g0 + u][3 + k];
+                g_lo += s_geo[g0 + u][9];
             }
-            g_ls[j] = gsj * s[j];
-        }
-        const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
-        float gq[4];
-        gq[0] = -2.f * z * gRq[1] + 2.f * y * gRq[2] + 2.f * z * gRq[3] - 2.f * x * gRq[5] - 2.f * y * gRq[6] +
-                2.f * x * gRq[7];
-        gq[1] = 2.f * y * gRq[1] + 2.f * z * gRq[2] + 2.f * y * gRq[3] - 4.f * x * gRq[4] - 2.f * w * gRq[5] +
-                2.f * z * gRq[6] + 2.f * w * gRq[7] - 4.f * x * gRq[8];
-        gq[2] = -4.f * y * gRq[0] + 2.f * x * gRq[1] + 2.f * w * gRq[2] + 2.f * x * gRq[3] + 2.f * z * gRq[5] -
-                2.f * w * gRq[6] + 2.f * z * gRq[7] - 4.f * y * gRq[8];
-        gq[3] = -4.f * z * gRq[0] - 2.f * w * gRq[1] + 2.f * x * gRq[2] + 2.f * w * gRq[3] - 4.f * z * gRq[4] +
-                2.f * y * gRq[5] + 2.f * x * gRq[6] + 2.f * y * gRq[7];
-        const float dq = gq[0] * qn[0] + gq[1] * qn[1] + gq[2] * qn[2] + gq[3] * qn[3];
-        float g_q[4];
+            for (int u = 0; u < P; ++u) {
+                n2[4] += s_n2[g0 + u][0];
+                n2[5] += s_n2[g0 + u][1];
+            }
+            // Sigma = M M^T, M = Rq diag(s):  dL/dM = 2 G M
+            const float Gf[9] = {G6[0], G6[1], G6[2], G6[1], G6[3], G6[4], G6[2], G6[4], G6[5]};
+            float gRq[9], g_ls[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) g_q[k] = (gq[k] - qn[k] * dq) * qi;
-        // lo = log2(sigmoid(logit)): dlo/dlogit = (1 - o) / ln 2
-        const float g_logit = g_lo * (1.f - o) / kLn2;
-
-        const int64_t st = a.g.stride;
-        float n2[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int jj = 0; jj < 3; ++jj) {
+                float gsj = 0.f;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            a.g.mean[k * st + t] = g_mu[k];
-            a.g.log_scale[k * st + t] = g_ls[k];
-            n2[0] += g_mu[k] * g_mu[k];
-            n2[1] += g_ls[k] * g_ls[k];
-        }
+                for (int i = 0; i < 3; ++i) {
+                    float gm = 0.f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a.g.quat[k * st + t] = g_q[k];
-            n2[2] += g_q[k] * g_q[k];
-        }
-        a.g.logit[t] = g_logit;
-        n2[3] = g_logit * g_logit;
+                    for (int k = 0; k < 3; ++k) gm += Gf[3 * i + k] * Rq[3 * k + jj] * s3[jj];
+                    gm *= 2.f;
+                    gsj += gm * Rq[3 * i + jj];
+                    gRq[3 * i + jj] = gm * s3[jj];
+                }
+                g_ls[jj] = gsj * s3[jj];
+            }
+            const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+            float gq[4];
+            gq[0] = -2.f * z * gRq[1] + 2.f * y * gRq[2] + 2.f * z * gRq[3] - 2.f * x * gRq[5] - 2.f * y * gRq[6] +
+                    2.f * x * gRq[7];
+            gq[1] = 2.f * y * gRq[1] + 2.f * z * gRq[2] + 2.f * y * gRq[3] - 4.f * x * gRq[4] - 2.f * w * gRq[5] +
+                    2.f * z * gRq[6] + 2.f * w * gRq[7] - 4.f * x * gRq[8];
+            gq[2] = -4.f * y * gRq[0] + 2.f * x * gRq[1] + 2.f * w * gRq[2] + 2.f * x * gRq[3] + 2.f * z * gRq[5] -
+                    2.f * w * gRq[6] + 2.f * z * gRq[7] - 4.f * y * gRq[8];
+            gq[3] = -4.f * z * gRq[0] - 2.f * w * gRq[1] + 2.f * x * gRq[2] + 2.f * w * gRq[3] - 4.f * z * gRq[4] +
+                    2.f * y * gRq[5] + 2.f * x * gRq[6] + 2.f * y * gRq[7];
+            const float dq = gq[0] * qn[0] + gq[1] * qn[1] + gq[2] * qn[2] + gq[3] * qn[3];
+            float g_q[4];
 #pragma unroll
-        for (int k = 0; k < 48; ++k) {
-            a.g.sh[k * st + t] = g_sh[k];
-            n2[4] += g_sh[k] * g_sh[k];
-        }
+            for (int k = 0; k < 4; ++k) g_q[k] = (gq[k] - qn[k] * dq) * qi;
+            // lo = log2(sigmoid(logit)): dlo/dlogit = (1 - o) / ln 2
+            const float o = 1.f / (1.f + expf(-a.sp.logit[id]));
+            const float g_logit = g_lo * (1.f - o) / kLn2;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            a.g.vsh[k * st + t] = g_vsh[k];
-            n2[5] += g_vsh[k] * g_vsh[k];
-        }
-        if (a.score) {
-            float sc = 0.f;
+            for (int k = 0; k < 3; ++k) {
+                a.g.mean[k * st + t] = g_mu[k];
+                a.g.log_scale[k * st + t] = g_ls[k];
+                n2[0] += g_mu[k] * g_mu[k];
+                n2[1] += g_ls[k] * g_ls[k];
+            }
 #pragma unroll
-            for (int k = 0; k < 6; ++k) sc = fmaxf(sc, sqrtf(n2[k]) / a.eps[k]);
-            a.score[id] = sc;
+            for (int k = 0; k < 4; ++k) {
+                a.g.quat[k * st + t] = g_q[k];
+                n2[2] += g_q[k] * g_q[k];
+            }
+            a.g.logit[t] = g_logit;
+            n2[3] = g_logit * g_logit;
+            if (a.score) {
+                float sc = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sc = fmaxf(sc, sqrtf(n2[k]) / a.eps[k]);
+                a.score[id] = sc;
+            }
         }
+        __syncthreads();
     }
     block_add_double(gsig, a.grad_sigma);
 }
@@ -730,8 +816,13 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
     a.grad_sigma = grad_sigma;
     a.score = score;
     for (int k = 0; k < 6; ++k) a.eps[k] = eps[k];
-    const unsigned blocks = (unsigned)((rl.Acap + 255) / 256);
-    if (blocks) hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(256), 0, s, a);
+    int P = 1;
+    while (P < b.n_views) P *= 2;
+    a.vlanes = P;
+    const int64_t rows_per_block = kPbThreads / P;
+    int64_t blocks = (rl.Acap + rows_per_block - 1) / rows_per_block;
+    if (blocks > kPbBlocks) blocks = kPbBlocks;
+    if (blocks > 0) hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)blocks), dim3(kPbThreads), 0, s, a);
 }
 
 }  // namespace oit

@@ -84,8 +84,35 @@ __device__ __forceinline__ bool tile_hit(const Rec &r, float tau, const CamDev &
 }
 
 // ---------------------------------------------------------------------------------
-// preprocess: one thread per listed splat, all views; writes the records, the tile
-// rectangles and counts the tile entries.
+// Work items of the per-record kernels: one (listed record, view) pair per item, the
+// records being the call's active rows and then its label changes.  The counts live
+// on the device, so the grid is fixed and strides over them.
+// ---------------------------------------------------------------------------------
+constexpr unsigned kRecBlocks = 2048;
+
+struct RecItems {
+    int64_t na, total;   // listed active rows; items = (na + n_delta) * views
+};
+
+__device__ __forceinline__ RecItems rec_items(const RowList &rl, int n_views)
+{
+    int64_t na = rl.n_active ? (int64_t)*rl.n_active : rl.n_active_host;
+    na = na < 0 ? 0 : (na > rl.Acap ? rl.Acap : na);
+    int64_t nd = rl.n_delta ? (int64_t)*rl.n_delta : 0;
+    const int64_t dcap = rl.Rcap - rl.Acap;
+    nd = nd < 0 ? 0 : (nd > dcap ? dcap : nd);
+    return RecItems{na, (na + nd) * n_views};
+}
+
+// record index of listed record k (active rows first, then label changes)
+__device__ __forceinline__ int64_t rec_of(const RowList &rl, int64_t na, int64_t k)
+{
+    return k < na ? k : rl.Acap + (k - na);
+}
+
+// ---------------------------------------------------------------------------------
+// preprocess: one thread per (listed record, view); projects the splat, writes the
+// record and its tile rectangle and counts the tile entries.
 // ---------------------------------------------------------------------------------
 struct PreArgs {
     SplatPtrs sp;    // active rows
@@ -95,106 +122,115 @@ struct PreArgs {
     Buffers b;
 };
 
-__global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
+__device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.rl.Rcap) return;
     int sign = 0;
     const int64_t id = record_row(a.rl, t, sign);
     if (id < 0) return;
     const SplatPtrs &sp = sign == 0 ? a.sp : a.dsp;
     const int64_t n = sp.n;
-    const float sigma = *a.sigma;
+    const CamDev &cam = a.b.cams[v];
+    const size_t ri = (size_t)v * a.rl.Rcap + t;
 
-    float mu[3], s[3], q[4];
+    float mu[3], s3[3], q[4];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         mu[k] = sp.mean[k * n + id];
-        s[k] = expf(sp.log_scale[k * n + id]);
+        s3[k] = expf(sp.log_scale[k * n + id]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = sp.quat[k * n + id];
     const float qi = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     float Rq[9], S6[6];
     quat_rot(q[0] * qi, q[1] * qi, q[2] * qi, q[3] * qi, Rq);
-    cov3d(Rq, s, S6);
-    const float lg = sp.logit[id];
-    const float lo = -log2f(1.f + expf(-lg));   // log2(sigmoid(logit))
-    float shc[48], vsc[16];
-#pragma unroll
-    for (int k = 0; k < 48; ++k) shc[k] = sp.sh[k * n + id];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) vsc[k] = sp.vsh[k * n + id];
+    cov3d(Rq, s3, S6);
 
-    const int S = a.b.tile;
-    for (int v = 0; v < a.b.n_views; ++v) {
-        const CamDev &cam = a.b.cams[v];
-        const size_t ri = (size_t)v * a.rl.Rcap + t;
-        Rec r;
-        short4 rect = make_short4(0, 0, 0, 0);
-        Geo g;
-        if (geometry(cam, mu, S6, g)) {
-            float dir[3] = {mu[0] - cam.cc[0], mu[1] - cam.cc[1], mu[2] - cam.cc[2]};
-            const float di = rsqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-            dir[0] *= di;
-            dir[1] *= di;
-            dir[2] *= di;
-            float Y[16];
-            sh_eval(dir[0], dir[1], dir[2], Y);
-            float col[3];
+    Rec r;
+    short4 rect = make_short4(0, 0, 0, 0);
+    Geo g;
+    if (geometry(cam, mu, S6, g)) {
+        const float lo = -log2f(1.f + expf(-sp.logit[id]));   // log2(sigmoid(logit))
+        float dir[3] = {mu[0] - cam.cc[0], mu[1] - cam.cc[1], mu[2] - cam.cc[2]};
+        const float di = rsqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        dir[0] *= di;
+        dir[1] *= di;
+        dir[2] *= di;
+        float Y[16];
+        sh_eval(dir[0], dir[1], dir[2], Y);
+        float col[3] = {kColorOffset, kColorOffset, kColorOffset};
+        float vr = kColorOffset;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float acc = kColorOffset;
+        for (int k = 0; k < 16; ++k) {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) acc += Y[k] * shc[3 * k + ch];
-                col[ch] = fmaxf(acc, 0.f);
-            }
-            float vr = kColorOffset;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) vr += Y[k] * vsc[k];
-            const float vv = fmaxf(vr, 0.f);
-            const float d = g.tc[2];
-            const bool w_on = d < sigma;
-            const float w = w_on ? (1.f - d / sigma) * vv : 0.f;
-            const float h = -0.5f * kLog2e;
-            r.a = make_float4(g.mx, g.my, h * g.con_a, 2.f * h * g.con_b);
-            r.b = make_float4(h * g.con_c, lo, col[0], col[1]);
-            if (sign == 0)
-                r.c = make_float4(col[2], w, 0.f, 1.f);
-            else
-                r.c = make_float4(col[2], w_on ? vv : 0.f, d, (float)sign);
-
-            const float tau = tile_tau(lo);
-            if (tau > 0.f) {
-                // footprint box of the (slightly widened) level set, in pixels, +1 px
-                const float tau_px = tau * 2.f * kLn2;   // back to units of the unscaled form
-                const float hx = sqrtf(tau_px * g.cov_a), hy = sqrtf(tau_px * g.cov_c);
-                const float xl = fminf(fmaxf(g.mx - hx - 0.5f, -1e7f), 1e7f);
-                const float xh = fminf(fmaxf(g.mx + hx - 0.5f, -1e7f), 1e7f);
-                const float yl = fminf(fmaxf(g.my - hy - 0.5f, -1e7f), 1e7f);
-                const float yh = fminf(fmaxf(g.my + hy - 0.5f, -1e7f), 1e7f);
-                int x0 = (int)floorf(xl) - 1, x1 = (int)ceilf(xh) + 1;
-                int y0 = (int)floorf(yl) - 1, y1 = (int)ceilf(yh) + 1;
-                x0 = max(x0, 0);
-                y0 = max(y0, 0);
-                x1 = min(x1, cam.W - 1);
-                y1 = min(y1, cam.H - 1);
-                if (x0 <= x1 && y0 <= y1) {
-                    rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
-                    uint32_t *cnt = sign == 0 ? a.b.cnt_a : a.b.cnt_d;
-                    for (int ty = rect.z; ty < rect.w; ++ty)
-                        for (int tx = rect.x; tx < rect.y; ++tx)
-                            if (tile_hit(r, tau, cam, S, tx, ty))
-                                atomicAdd(&cnt[cam.tile_base + ty * cam.tiles_x + tx], 1u);
-                }
-            }
-        } else {
-            r.a = make_float4(0.f, 0.f, 0.f, 0.f);
-            r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
-            r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * sp.sh[(3 * k + ch) * n + id];
+            vr += Y[k] * sp.vsh[k * n + id];
         }
-        a.b.rec[ri] = r;
-        a.b.rect[ri] = rect;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.f);
+        const float vv = fmaxf(vr, 0.f);
+        const float sigma = *a.sigma;
+        const float d = g.tc[2];
+        const bool w_on = d < sigma;
+        const float w = w_on ? (1.f - d / sigma) * vv : 0.f;
+        const float h = -0.5f * kLog2e;
+        r.a = make_float4(g.mx, g.my, h * g.con_a, 2.f * h * g.con_b);
+        r.b = make_float4(h * g.con_c, lo, col[0], col[1]);
+        if (sign == 0)
+            r.c = make_float4(col[2], w, 0.f, 1.f);
+        else
+            r.c = make_float4(col[2], w_on ? vv : 0.f, d, (float)sign);
+
+        const float tau = tile_tau(lo);
+        if (tau > 0.f) {
+            // footprint box of the (slightly widened) level set, in pixels, +1 px
+            const float tau_px = tau * 2.f * kLn2;   // back to units of the unscaled form
+            const float hx = sqrtf(tau_px * g.cov_a), hy = sqrtf(tau_px * g.cov_c);
+            const float xl = fminf(fmaxf(g.mx - hx - 0.5f, -1e7f), 1e7f);
+            const float xh = fminf(fmaxf(g.mx + hx - 0.5f, -1e7f), 1e7f);
+            const float yl = fminf(fmaxf(g.my - hy - 0.5f, -1e7f), 1e7f);
+            const float yh = fminf(fmaxf(g.my + hy - 0.5f, -1e7f), 1e7f);
+            int x0 = (int)floorf(xl) - 1, x1 = (int)ceilf(xh) + 1;
+            int y0 = (int)floorf(yl) - 1, y1 = (int)ceilf(yh) + 1;
+            x0 = max(x0, 0);
+            y0 = max(y0, 0);
+            x1 = min(x1, cam.W - 1);
+            y1 = min(y1, cam.H - 1);
+            if (x0 <= x1 && y0 <= y1) {
+                const int S = a.b.tile;
+                rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
+                uint32_t *cnt = sign == 0 ? a.b.cnt_a : a.b.cnt_d;
+                for (int ty = rect.z; ty < rect.w; ++ty)
+                    for (int tx = rect.x; tx < rect.y; ++tx)
+                        if (tile_hit(r, tau, cam, S, tx, ty))
+                            atomicAdd(&cnt[cam.tile_base + ty * cam.tiles_x + tx], 1u);
+            }
+        }
+    } else {
+        r.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
+        r.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    a.b.rec[ri] = r;
+    a.b.rect[ri] = rect;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
+{
+    const int V = a.b.n_views;
+    const RecItems it = rec_items(a.rl, V);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t sk = stride / V, sv = stride % V;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k = i / V;
+    int v = (int)(i % V);
+    for (; i < it.total; i += stride) {
+        preprocess_one(a, rec_of(a.rl, it.na, k), v);
+        k += sk;
+        v += (int)sv;
+        if (v >= V) {
+            v -= V;
+            ++k;
+        }
     }
 }
 
@@ -202,8 +238,7 @@ void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const fl
                              const Buffers &b, hipStream_t s)
 {
     PreArgs a{sp, dsp, sigma, rl, b};
-    const unsigned blocks = (unsigned)((rl.Rcap + 255) / 256);
-    if (blocks) hipLaunchKernelGGL(k_preprocess_count, dim3(blocks), dim3(256), 0, s, a);
+    if (rl.Rcap > 0) hipLaunchKernelGGL(k_preprocess_count, dim3(kRecBlocks), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -267,52 +302,70 @@ struct EmitArgs {
     Buffers b;
 };
 
-__global__ __launch_bounds__(256) void k_emit(EmitArgs a)
+__device__ void emit_one(const EmitArgs &a, int64_t t, int v)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.rl.Rcap) return;
     int sign = 0;
     if (record_row(a.rl, t, sign) < 0) return;
+    const CamDev &cam = a.b.cams[v];
+    const size_t ri = (size_t)v * a.rl.Rcap + t;
+    const short4 rect = a.b.rect[ri];
+    if (rect.x >= rect.y || rect.z >= rect.w) return;
     const int S = a.b.tile;
     const uint64_t cap = (uint64_t)a.b.pair_cap;
-    for (int v = 0; v < a.b.n_views; ++v) {
-        const CamDev &cam = a.b.cams[v];
-        const size_t ri = (size_t)v * a.rl.Rcap + t;
-        const short4 rect = a.b.rect[ri];
-        if (rect.x >= rect.y || rect.z >= rect.w) continue;
-        const Rec r = a.b.rec[ri];
-        const float tau = tile_tau(r.b.y);
-        for (int ty = rect.z; ty < rect.w; ++ty)
-            for (int tx = rect.x; tx < rect.y; ++tx) {
-                if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
-                const int tile = cam.tile_base + ty * cam.tiles_x + tx;
-                uint64_t pos;
-                if (sign == 0) {
-                    const uint32_t slot = atomicAdd(&a.b.fill_a[tile], 1u);
-                    if (slot >= a.b.cnt_a[tile]) continue;
-                    pos = (uint64_t)a.b.tile_off[tile] + slot;
-                } else {
-                    const uint32_t slot = atomicAdd(&a.b.fill_d[tile], 1u);
-                    if (slot >= a.b.cnt_d[tile]) continue;
-                    pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
-                }
-                if (pos < cap) a.b.entries[pos] = (uint32_t)t;
+    const Rec r = a.b.rec[ri];
+    const float tau = tile_tau(r.b.y);
+    for (int ty = rect.z; ty < rect.w; ++ty)
+        for (int tx = rect.x; tx < rect.y; ++tx) {
+            if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
+            const int tile = cam.tile_base + ty * cam.tiles_x + tx;
+            uint64_t pos;
+            if (sign == 0) {
+                const uint32_t slot = atomicAdd(&a.b.fill_a[tile], 1u);
+                if (slot >= a.b.cnt_a[tile]) continue;
+                pos = (uint64_t)a.b.tile_off[tile] + slot;
+            } else {
+                const uint32_t slot = atomicAdd(&a.b.fill_d[tile], 1u);
+                if (slot >= a.b.cnt_d[tile]) continue;
+                pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
             }
+            if (pos < cap) a.b.entries[pos] = (uint32_t)t;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_emit(EmitArgs a)
+{
+    const int V = a.b.n_views;
+    const RecItems it = rec_items(a.rl, V);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t sk = stride / V, sv = stride % V;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k = i / V;
+    int v = (int)(i % V);
+    for (; i < it.total; i += stride) {
+        emit_one(a, rec_of(a.rl, it.na, k), v);
+        k += sk;
+        v += (int)sv;
+        if (v >= V) {
+            v -= V;
+            ++k;
+        }
     }
 }
 
 void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s)
 {
     EmitArgs a{rl, b};
-    const unsigned blocks = (unsigned)((rl.Rcap + 255) / 256);
-    if (blocks) hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, a);
+    if (rl.Rcap > 0) hipLaunchKernelGGL(k_emit, dim3(kRecBlocks), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------------
 // raster forward: one workgroup per tile (all views of the batch in one launch).
 // Records of the tile's entries are staged through LDS in batches; every thread
-// blends them into its pixels in list order (no depth order).  A thread's pixels
-// share one column, so the per-column exponent terms are formed once per record.
+// blends them into its pixels in list order (no depth order).  Each wave owns a
+// compact block of the tile (16 x 16 pixels for 32-pixel tiles, else 8 x 8), and the
+// staging step marks which blocks a record's footprint box reaches, so a wave skips
+// the records that cannot touch its pixels.  A thread's pixels share one column, so
+// the per-column exponent terms are formed once per record.
 // ---------------------------------------------------------------------------------
 struct FwdArgs {
     Buffers b;
@@ -326,21 +379,44 @@ struct FwdArgs {
 __device__ const Rec kNoRec = {{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 
 // Stage record r for a tile whose first pixel centre is (x0, y0): the mean is
-// replaced by the offsets x0 - mx, y0 - my of the exponent form.
-__device__ __forceinline__ void stage_rec(float4 *dst, const Rec &r, float x0, float y0)
+// replaced by the offsets x0 - mx, y0 - my of the exponent form.  Returns the mask of
+// the tile's pixel blocks (BW x BW, WPR per row, NW in all) that the footprint box of
+// the record's (slightly widened) alpha >= 1/255 level set reaches.
+template <int BW, int WPR, int NW>
+__device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, float y0)
 {
-    dst[0] = make_float4(x0 - r.a.x, y0 - r.a.y, r.a.z, r.a.w);
+    const float dx0 = x0 - r.a.x, dy0 = y0 - r.a.y;
+    dst[0] = make_float4(dx0, dy0, r.a.z, r.a.w);
     dst[1] = r.b;
     dst[2] = r.c;
+    const float A = -r.a.z, B = -0.5f * r.a.w, C = -r.b.x;
+    const float det = A * C - B * B;
+    const float tau = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
+    if (!(tau > 0.f && det > 0.f)) return 0;
+    const float hx = sqrtf(tau * C / det) + 0.01f, hy = sqrtf(tau * A / det) + 0.01f;
+    int mask = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const float bx = dx0 + (float)((w % WPR) * BW), by = dy0 + (float)((w / WPR) * BW);
+        if (bx <= hx && bx + (float)(BW - 1) >= -hx && by <= hy && by + (float)(BW - 1) >= -hy) mask |= 1 << w;
+    }
+    return mask;
 }
 
-template <int S, int BATCH>
+// BAU = true: the label-change pass (blend-and-update of the pre-rendered buffer);
+// it runs first, as its own launch.  BAU = false: the active pass and the image.
+template <int S, int BATCH, bool BAU>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArgs a)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     constexpr int PPT = S * S / NT;
-    constexpr int RSTEP = NT / S;   // rows between one thread's pixels
+    constexpr int BW = S == 32 ? 16 : 8;   // edge of a wave's pixel block
+    constexpr int WPR = S / BW;            // blocks per tile row
+    constexpr int NW = NT / 64;            // waves (= blocks)
+    constexpr int RSTEP = 64 / BW;         // rows between one thread's pixels
+    static_assert(NW == WPR * WPR && PPT * RSTEP == BW, "wave blocks must tile the tile");
     __shared__ float4 s_rec[BATCH * 3];
+    __shared__ int s_mask[BATCH];
 
     const int tile = blockIdx.x;
     const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
@@ -348,7 +424,9 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     const int lt = tile - cam.tile_base;
     const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
-    const int col = threadIdx.x % S, row0 = threadIdx.x / S;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wbit = 1 << wave;
+    const int col = (wave % WPR) * BW + lane % BW, row0 = (wave / WPR) * BW + lane / BW;
     const float colf = (float)col;
     const bool col_in = tx * S + col < cam.W;
     const size_t HW = (size_t)cam.W * cam.H;
@@ -372,25 +450,38 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     if (off + na + nd > cap) nd = off + na < cap ? cap - off - na : 0;
     const Rec *recv = a.b.rec + (size_t)v * a.b.Rcap;
 
-    // label changes first: BAU accumulators (sign-weighted, sigma-free), folded into
-    // the pre-rendered buffer before the active pass so that they are not live there
-    if (nd) {
-        float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT];
+    // label changes: BAU accumulators (sign-weighted, sigma-free), added to the
+    // pre-rendered buffer
+    if constexpr (BAU) {
+        if (nd == 0 || a.pre == nullptr) return;
+        // log T changes by sum sign * ln(1 - alpha): the factors of each sign are
+        // multiplied (Tp: +1, Tm: -1) and folded into dL every kFold records, before
+        // a product of factors >= 1 - kAlphaMax can underflow
+        constexpr int kFold = 16;
+        float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT], Tp[PPT], Tm[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
             dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
             dQ0[p] = dQ1[p] = dL[p] = 0.f;
+            Tp[p] = Tm[p] = 1.f;
         }
+        int since_fold = 0;
         for (uint64_t base = 0; base < nd; base += BATCH) {
             const int cnt = (int)(nd - base < (uint64_t)BATCH ? nd - base : (uint64_t)BATCH);
             __syncthreads();
             for (int j = threadIdx.x; j < cnt; j += NT) {
                 const uint32_t ri = a.b.entries[off + na + base + j];
-                stage_rec(&s_rec[3 * j], (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec, x0, y0);
+                s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j],
+                                                   (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec, x0, y0);
             }
             __syncthreads();
-            for (int j = 0; j < cnt; ++j) {
+            for (int sb = 0; sb < cnt; sb += 64) {
+              // the staged records that reach this wave's block, one bit each
+              uint64_t todo = __ballot(sb + lane < cnt && (s_mask[sb + lane] & wbit));
+              while (todo) {
+                const int j = sb + (int)__builtin_ctzll(todo);
+                todo &= todo - 1;
                 const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
                 const float dx = ra.x + colf;
                 const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
@@ -409,23 +500,36 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                         dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
                         dQ0[p] += sav;
                         dQ1[p] += savd;
-                        dL[p] = fmaf(rc.w, __builtin_amdgcn_logf(1.f - al) * kLn2, dL[p]);
+                        if (rc.w > 0.f)
+                            Tp[p] *= 1.f - al;
+                        else
+                            Tm[p] *= 1.f - al;
                     }
                 }
+                if (++since_fold == kFold) {
+                    since_fold = 0;
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        dL[p] += (__builtin_amdgcn_logf(Tp[p]) - __builtin_amdgcn_logf(Tm[p])) * kLn2;
+                        Tp[p] = Tm[p] = 1.f;
+                    }
+                }
+              }
             }
         }
-        if (a.pre) {
 #pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                if (!in[p]) continue;
-                const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
-                float *pr = a.pre + 9 * pb + pix;
-                const float add[9] = {dP0[p][0], dP0[p][1], dP0[p][2], dP1[p][0], dP1[p][1],
-                                      dP1[p][2], dQ0[p],    dQ1[p],    dL[p]};
+        for (int p = 0; p < PPT; ++p) dL[p] += (__builtin_amdgcn_logf(Tp[p]) - __builtin_amdgcn_logf(Tm[p])) * kLn2;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) pr[k * HW] += add[k];
-            }
+        for (int p = 0; p < PPT; ++p) {
+            if (!in[p]) continue;
+            const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
+            float *pr = a.pre + 9 * pb + pix;
+            const float add[9] = {dP0[p][0], dP0[p][1], dP0[p][2], dP1[p][0], dP1[p][1],
+                                  dP1[p][2], dQ0[p],    dQ1[p],    dL[p]};
+#pragma unroll
+            for (int k = 0; k < 9; ++k) pr[k * HW] += add[k];
         }
+        return;
     }
 
     // active entries: BAN accumulators
@@ -442,10 +546,14 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
         __syncthreads();
         for (int j = threadIdx.x; j < cnt; j += NT) {
             const uint32_t ri = a.b.entries[off + base + j];
-            stage_rec(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
+            s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
         }
         __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
+        for (int sb = 0; sb < cnt; sb += 64) {
+          uint64_t todo = __ballot(sb + lane < cnt && (s_mask[sb + lane] & wbit));
+          while (todo) {
+            const int j = sb + (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
             const float dx = ra.x + colf;
             const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
@@ -464,6 +572,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
                     T[p] *= 1.f - al;
                 }
             }
+          }
         }
     }
 
@@ -514,18 +623,25 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     }
 }
 
-template <int S>
+template <int S, bool BAU>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
-    case 32: hipLaunchKernelGGL((k_raster_fwd<S, 32>), grid, block, 0, s, a); return true;
-    case 64: hipLaunchKernelGGL((k_raster_fwd<S, 64>), grid, block, 0, s, a); return true;
-    case 128: hipLaunchKernelGGL((k_raster_fwd<S, 128>), grid, block, 0, s, a); return true;
-    case 256: hipLaunchKernelGGL((k_raster_fwd<S, 256>), grid, block, 0, s, a); return true;
+    case 32: hipLaunchKernelGGL((k_raster_fwd<S, 32, BAU>), grid, block, 0, s, a); return true;
+    case 64: hipLaunchKernelGGL((k_raster_fwd<S, 64, BAU>), grid, block, 0, s, a); return true;
+    case 128: hipLaunchKernelGGL((k_raster_fwd<S, 128, BAU>), grid, block, 0, s, a); return true;
+    case 256: hipLaunchKernelGGL((k_raster_fwd<S, 256, BAU>), grid, block, 0, s, a); return true;
     default: return false;
     }
+}
+
+template <int S>
+static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s)
+{
+    if (a.pre && !raster_fwd_s<S, true>(a, batch, s)) return false;
+    return raster_fwd_s<S, false>(a, batch, s);
 }
 
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
@@ -534,9 +650,9 @@ bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], 
     FwdArgs a{b, sigma, bg[0], bg[1], bg[2], pre, image, pixstate};
     if (b.T == 0) return true;
     switch (b.tile) {
-    case 8: return raster_fwd_s<8>(a, batch, s);
-    case 16: return raster_fwd_s<16>(a, batch, s);
-    case 32: return raster_fwd_s<32>(a, batch, s);
+    case 8: return raster_fwd_both<8>(a, batch, s);
+    case 16: return raster_fwd_both<16>(a, batch, s);
+    case 32: return raster_fwd_both<32>(a, batch, s);
     default: return false;
     }
 }
