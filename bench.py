@@ -30,6 +30,45 @@ FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 10, 12
 BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 10, 39
 
 
+KERNEL_SOURCES = {
+    "k_raster_bwd": ("k_backward.hip", "oit_device.h", "oit_internal.h"),
+    "k_raster_fwd": ("k_forward.hip", "oit_device.h", "oit_internal.h"),
+}
+
+
+def kernel_source_hash(kname):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kname]:
+        with open(os.path.join(ROOT, "paper_2605_13855_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kname, tile, batch):
+    """HBM bytes per launch of `kname` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (profiles/<kname>_traffic.txt), or None when there is none for this tiling or
+    the kernel's sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kname}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    try:
+        if fields.get("source_sha256") != kernel_source_hash(kname):
+            return None
+        # the backward kernel does not depend on the forward's staging batch
+        if int(fields["tile"]) != tile or (kname == "k_raster_fwd" and int(fields["batch"]) != batch):
+            return None
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -51,26 +90,37 @@ def prime(trainer):
 
 
 def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=False):
+    """Time one form of the step.  The autotuner, if asked, runs on a throwaway trainer,
+    so the timed trainer starts from the same state with or without it.  Graph replays
+    (or eager steps) give the step time; a short eager pass after them times the
+    raster kernels with start/stop events that bracket exactly the kernel (events
+    recorded inside a captured graph do not wait for the preceding kernel)."""
     import torch
     from paper_2605_13855_amd import oit
     from paper_2605_13855_amd.render import ActiveSetTrainer
 
     name = "dense" if dense else f"active {fraction:.0%}"
+    tuned = None
+    if tune:
+        from paper_2605_13855_amd.autotune import autotune
+        log(f"{name}: autotune")
+        t = ActiveSetTrainer(scene, fraction=fraction, tile=tile, batch=batch, dense=dense)
+        if not dense:
+            t.warmup_dense_scores()
+        prime(t)
+        (tile, batch), res = autotune(t, log=log)
+        tuned = {"tile": tile, "batch": batch, "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in res.items()}}
+        del t
+        torch.cuda.empty_cache()
     log(f"{name}: building trainer")
     t = ActiveSetTrainer(scene, fraction=fraction, tile=tile, batch=batch, dense=dense)
     if not dense:
         t.warmup_dense_scores()
     prime(t)
-    tuned = None
-    if tune:
-        from paper_2605_13855_amd.autotune import autotune
-        (bt, bb), res = autotune(t, log=log)
-        tuned = {"tile": bt, "batch": bb, "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in res.items()}}
     # headroom for the tile lists of later steps (the active set moves)
     need = t.r.pairs_needed()
     t.r.set_tuning(pair_capacity=min(int(need * 1.5) + 65536, 2 ** 32 - 2))
     log(f"{name}: tile={t.r.tuning.tile} batch={t.r.tuning.batch} pair_capacity={t.r.tuning.pair_capacity}")
-    oit.timing_enable(True)
     step = t.iteration if eager else t.replay
     if not eager:
         t.capture()
@@ -78,9 +128,8 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         step()
     torch.cuda.synchronize()
     oit.clear_status(t.r.ws)
-    log(f"{name}: timing {steps} graph replays")
-    step_ms, fwd_ms, bwd_ms, pairs, evals = [], [], [], [], []
-    torch.cuda.synchronize()
+    log(f"{name}: timing {steps} {'eager steps' if eager else 'graph replays'}")
+    step_ms, pairs, evals, entries, chunks = [], [], [], [], []
     for _ in range(steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -88,34 +137,50 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         e1.record()
         torch.cuda.synchronize()
         step_ms.append(e0.elapsed_time(e1))
+        c = t.r.counters()
+        entries.append(c[0])
+        pairs.append(c[1])
+        evals.append(c[2])
+        chunks.append(c[3])
+    # kernel timing pass: eager steps with kernel-bracketing events, and the pair
+    # counters of the same launches
+    ksteps = max(3, steps // 2)
+    oit.timing_enable(True)
+    fwd_ms, bwd_ms, kpairs, kevals = [], [], [], []
+    for _ in range(ksteps):
+        t.iteration()
         f, b = oit.timing_read()
         fwd_ms.append(f)
         bwd_ms.append(b)
         c = t.r.counters()
-        pairs.append(c[1])
-        evals.append(c[2])
-    torch.cuda.synchronize()
+        kpairs.append(c[1])
+        kevals.append(c[2])
     oit.timing_enable(False)
+    torch.cuda.synchronize()
     st = t.r.status()
     if st:
         raise RuntimeError(f"device status {st} during the timed steps")
     loss = float(t.loss.item())
-    n_active = t.k
     out = {
         "ms_per_step": statistics.mean(step_ms),
         "ms_per_step_median": statistics.median(step_ms),
         "raster_fwd_ms": statistics.mean(fwd_ms),
         "raster_bwd_ms": statistics.mean(bwd_ms),
+        "kernel_steps": ksteps,
+        "kernel_pairs": statistics.mean(kpairs),
+        "kernel_evals": statistics.mean(kevals),
         "pairs": statistics.mean(pairs),
         "evals": statistics.mean(evals),
+        "entries": statistics.mean(entries),
+        "chunks": statistics.mean(chunks),
         "loss": loss,
-        "active": n_active,
+        "active": t.k,
         "tile": t.r.tuning.tile,
         "batch": t.r.tuning.batch,
         "tuned": tuned,
     }
-    log(f"{name}: {out['ms_per_step']:.3f} ms/step (raster fwd {out['raster_fwd_ms']:.3f} ms, "
-        f"bwd {out['raster_bwd_ms']:.3f} ms), {out['pairs']:.3e} contributing pairs")
+    log(f"{name}: {out['ms_per_step']:.3f} ms/step; raster fwd {out['raster_fwd_ms']:.3f} ms, "
+        f"bwd {out['raster_bwd_ms']:.3f} ms per launch; {out['pairs']:.3e} contributing pairs")
     del t
     torch.cuda.empty_cache()
     return out
@@ -241,17 +306,19 @@ def main():
         dense = run_form(scene, True, max(3, args.steps // 4), max(1, args.warmup // 2), 1.0, act["tile"],
                          act["batch"], False, args.eager)
 
-    # dominant kernel of the active step, roofline against the FP32 vector peak
-    fwd_flops = act["evals"] * FWD_FLOP_EVAL + act["pairs"] * FWD_FLOP_CONTRIB
-    bwd_flops = act["evals"] * BWD_FLOP_EVAL + act["pairs"] * BWD_FLOP_CONTRIB
+    # dominant kernel of the active step, roofline against the FP32 vector peak; flops
+    # from the pair counters of the launches that were timed
+    fwd_flops = act["kernel_evals"] * FWD_FLOP_EVAL + act["kernel_pairs"] * FWD_FLOP_CONTRIB
+    bwd_flops = act["kernel_evals"] * BWD_FLOP_EVAL + act["kernel_pairs"] * BWD_FLOP_CONTRIB
     if act["raster_bwd_ms"] >= act["raster_fwd_ms"]:
         kname, kms, kflops = "k_raster_bwd", act["raster_bwd_ms"], bwd_flops
     else:
         kname, kms, kflops = "k_raster_fwd", act["raster_fwd_ms"], fwd_flops
     achieved = kflops / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "flops_per_launch": kflops, "avg_launch_ms": round(kms, 4)}
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": committed_traffic(kname, act["tile"], act["batch"]),
+                "flops_per_launch": kflops, "avg_launch_ms": round(kms, 4), "timed_launches": act["kernel_steps"]}
     cpu = None if args.no_cpu else cpu_baseline(scene)
 
     value = act["pairs"] / (act["ms_per_step"] * 1e-3)
@@ -278,6 +345,7 @@ def main():
         },
         "active": {"ms_per_step": round(act["ms_per_step"], 4), "ms_median": round(act["ms_per_step_median"], 4),
                    "evals_per_s": value, "contributing_pairs": act["pairs"], "evaluated_pairs": act["evals"],
+                   "tile_entries": act["entries"], "bwd_work_items": act["chunks"],
                    "raster_fwd_ms": round(act["raster_fwd_ms"], 4), "raster_bwd_ms": round(act["raster_bwd_ms"], 4),
                    "loss": act["loss"], "autotune": act["tuned"]},
         "roofline": roofline,
@@ -287,6 +355,7 @@ def main():
         line["dense"] = {"ms_per_step": round(dense["ms_per_step"], 4),
                          "evals_per_s": dense["pairs"] / (dense["ms_per_step"] * 1e-3),
                          "contributing_pairs": dense["pairs"], "evaluated_pairs": dense["evals"],
+                         "tile_entries": dense["entries"], "bwd_work_items": dense["chunks"],
                          "raster_fwd_ms": round(dense["raster_fwd_ms"], 4),
                          "raster_bwd_ms": round(dense["raster_bwd_ms"], 4)}
         line["speedup_active_vs_dense"] = round(dense["ms_per_step"] / act["ms_per_step"], 3)

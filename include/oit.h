@@ -307,16 +307,20 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
                              int64_t *out, oit_stream stream);
 
 /*
- * Timing of the two raster kernels, for benchmarks.  While enabled (on != 0), every
- * oit_render_fwd records a pair of HIP events around its raster kernel and every
- * oit_render_bwd around its raster kernel, on the call's stream (also when captured
- * in a graph).  The events are created once by the first enable and owned by the
- * library; the setting is process-wide and not synchronised between threads.
+ * Timing of the raster kernels, for benchmarks.  While enabled (on != 0), every
+ * oit_render_fwd launches its raster kernels (the label-change pass when `pre` is
+ * given, then the active pass) and every oit_render_bwd its raster kernel with HIP
+ * events that the runtime records when the kernel starts and when it ends.  Eager
+ * launches only: a render call on a stream that is being captured fails with
+ * OIT_ERR_INVALID while timing is on.  The events are created once by the first
+ * enable and owned by the library; the setting is process-wide and not synchronised
+ * between threads.
  */
 oit_status oit_timing_enable(int32_t on);
 
 /* Wait for the last recorded events; out (host) [2] = milliseconds of the last
- * forward and backward raster kernel (-1 if not recorded). */
+ * forward raster kernels (label-change pass plus active pass) and of the last
+ * backward raster kernel (-1 if not recorded). */
 oit_status oit_timing_read(float *out);
 
 /* Clear the status word (enqueued on `stream`). */

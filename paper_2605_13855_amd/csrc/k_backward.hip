@@ -1,6 +1,8 @@
 // Backward pass: L1 loss gradient, per-pixel constants of the OIT partials, the
 // per-splat raster backward and the chain rule to the splat parameters and sigma
 // (App. B, Eqs. "oit_rendering_md" and "oit_rendering_detail").
+#include <hip/hip_ext.h>
+
 #include "oit_internal.h"
 
 namespace oit {
@@ -148,8 +150,9 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // processed), then every lane walks the 64 pixels column by column and reads each
 // pixel's constants as a uniform LDS broadcast.  Per splat, the colour and weight
 // sums and the moments of dL/de over the pixel offsets stay in registers; they give
-// the 10 screen-space partials once per work item, added to the per-(view, record)
-// gradient with one atomic per component.
+// the 10 screen-space partials once per work item, stored with plain stores in the
+// entry's own row (no atomics: the preprocess backward gathers a (record, view)
+// pair's rows through its gather list, in a fixed order).
 //
 // The work items are split into 8 contiguous ranges, one per XCD, so that the waves
 // that share a tile's pixel constants share an L2; a wave whose range is drained
@@ -171,6 +174,65 @@ __global__ __launch_bounds__(256) void k_chunk_map(Buffers b)
     if (t >= b.T) return;
     const uint32_t c1 = min(b.chunk_off[t + 1], b.max_chunks);
     for (uint32_t c = b.chunk_off[t]; c < c1; ++c) b.chunk_tile[c] = (uint32_t)t;
+}
+
+// Per-lane sums of the backward over the pixels of its tile entry.
+struct BwdSums {
+    float g_cr, g_cg, g_cb, g_w;
+    // moments of dL/de (without the ln 2 of d alpha / de) over the pixel offsets
+    float m0, m_x, m_y, m_xx, m_xy, m_yy;
+};
+
+// One staged 8 x 8 group for one lane's splat, column by column.  CAP: some splat of
+// the work item may reach the opacity cap, so alpha is clamped to 0.99 and its
+// derivative cut where it is; otherwise every alpha stays below 0.99 (the splats'
+// opacities are below it with a margin) and neither step is needed.
+template <bool CAP>
+__device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, int gxp, int gyp, float dx0, float dy0,
+                                          float qa, float qb, float qc, float lo, float cr, float cg, float cb,
+                                          float w, BwdSums &o)
+{
+    float dy[kGroup];
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r) dy[r] = dy0 + (float)(gyp + r);
+    // columns stay a loop: unrolled, the per-column moment updates are deferred and
+    // every column's partial sums stay live
+#pragma unroll 1
+    for (int c = 0; c < kGroup; ++c) {
+        const float dx = dx0 + (float)(gxp + c);
+        const float kb = exp_col_b(qb, dx), kc = exp_col_c(qa, lo, dx);
+        float c0 = 0.f, cy = 0.f, cyy = 0.f;
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+            const float e = exp_pix(qc, dy[r], kb, kc);
+            if (e >= kLog2AlphaMin) {
+                const float4 pc = pcs[r * kGroup + c];
+                const float Bc = pBs[r * kGroup + c];
+                const float ex = __builtin_amdgcn_exp2f(e);
+                const float al = CAP ? fminf(ex, kAlphaMax) : ex;
+                // A . c - s1 (pc.w holds -s1)
+                const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
+                const float aw = al * w;
+                o.g_cr = fmaf(pc.x, aw, o.g_cr);
+                o.g_cg = fmaf(pc.y, aw, o.g_cg);
+                o.g_cb = fmaf(pc.z, aw, o.g_cb);
+                o.g_w = fmaf(al, diff, o.g_w);
+                // dL/de / ln 2 = alpha (B / (1 - alpha) + w diff); zero where alpha is capped
+                const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                const float dLde = (CAP ? (al < kAlphaMax ? al : 0.f) : al) * dLda;
+                c0 += dLde;
+                const float ey = dLde * dy[r];
+                cy += ey;
+                cyy = fmaf(ey, dy[r], cyy);
+            }
+        }
+        o.m0 += c0;
+        o.m_x = fmaf(dx, c0, o.m_x);
+        o.m_xx = fmaf(dx * dx, c0, o.m_xx);
+        o.m_y += cy;
+        o.m_xy = fmaf(dx, cy, o.m_xy);
+        o.m_yy += cyy;
+    }
 }
 
 template <int S>
@@ -215,6 +277,8 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
             hy = sqrtf(tau * A / det) + 0.01f;
         }
     }
+    // this entry's row of screen-space partials (written for every valid lane)
+    float *dst = b.ep + (off + j) * kEpStride;
     // bit g: some lane's footprint box reaches group g (pixel offsets [g0, g0 + 7])
     uint32_t mask = 0;
 #pragma unroll
@@ -224,7 +288,14 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
                          gy0 + (float)(kGroup - 1) >= -hy;
         if (__ballot(hit)) mask |= 1u << g;
     }
-    if (mask == 0) return;
+    if (mask == 0) {
+        if (valid) {
+            ((float4 *)dst)[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            ((float4 *)dst)[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            ((float2 *)dst)[4] = make_float2(0.f, 0.f);
+        }
+        return;
+    }
 
     // this lane's pixel when staging a group's constants
     const int sx = lane % kGroup, sy = lane / kGroup;
@@ -240,9 +311,8 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
     };
 
-    float g_cr = 0.f, g_cg = 0.f, g_cb = 0.f, g_w = 0.f;
-    // moments of dL/de (without the ln 2 of d alpha / de) over the pixel offsets
-    float m0 = 0.f, m_x = 0.f, m_y = 0.f, m_xx = 0.f, m_xy = 0.f, m_yy = 0.f;
+    BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const bool may_cap = __ballot(valid && lo > kLog2NoCap) != 0;
     int g = __builtin_ctz(mask);
     mask &= mask - 1;
     float4 nc;
@@ -259,46 +329,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
         __builtin_amdgcn_wave_barrier();
         const int gxp = (g % GX) * kGroup, gyp = (g / GX) * kGroup;
-        float dy[kGroup];
-#pragma unroll
-        for (int r = 0; r < kGroup; ++r) dy[r] = dy0 + (float)(gyp + r);
-        // columns stay a loop: unrolled, the per-column moment updates are deferred and
-        // every column's partial sums stay live
-#pragma unroll 1
-        for (int c = 0; c < kGroup; ++c) {
-            const float dx = dx0 + (float)(gxp + c);
-            const float kb = exp_col_b(qb, dx), kc = exp_col_c(qa, lo, dx);
-            float c0 = 0.f, cy = 0.f, cyy = 0.f;
-#pragma unroll
-            for (int r = 0; r < kGroup; ++r) {
-                const float e = exp_pix(qc, dy[r], kb, kc);
-                if (e >= kLog2AlphaMin) {
-                    const float4 pc = s_c[wave][r * kGroup + c];
-                    const float Bc = s_B[wave][r * kGroup + c];
-                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
-                    const float kal = al < kAlphaMax ? al : 0.f;   // d alpha / de / ln 2; 0 when capped
-                    // A . c - s1 (pc.w holds -s1)
-                    const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
-                    const float aw = al * w;
-                    g_cr = fmaf(pc.x, aw, g_cr);
-                    g_cg = fmaf(pc.y, aw, g_cg);
-                    g_cb = fmaf(pc.z, aw, g_cb);
-                    g_w = fmaf(al, diff, g_w);
-                    // dL/dalpha = B / (1 - alpha) + w diff
-                    const float dLde = kal * fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
-                    const float ey = dLde * dy[r];
-                    c0 += dLde;
-                    cy += ey;
-                    cyy = fmaf(ey, dy[r], cyy);
-                }
-            }
-            m0 += c0;
-            m_x = fmaf(dx, c0, m_x);
-            m_xx = fmaf(dx * dx, c0, m_xx);
-            m_y += cy;
-            m_xy = fmaf(dx, cy, m_xy);
-            m_yy += cyy;
-        }
+        if (may_cap)
+            bwd_group<true>(s_c[wave], s_B[wave], gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
+        else
+            bwd_group<false>(s_c[wave], s_B[wave], gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
         __builtin_amdgcn_wave_barrier();
         if (gn < 0) break;
         g = gn;
@@ -306,20 +340,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     if (valid) {
         // de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
         // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
-        float *dst = b.sgrad + ((size_t)v * b.Acap + rj) * 10;
-        const float vals[10] = {-(2.f * qa * m_x + qb * m_y) * kLn2,
-                                -(qb * m_x + 2.f * qc * m_y) * kLn2,
-                                m_xx * kLn2,
-                                m_xy * kLn2,
-                                m_yy * kLn2,
-                                m0 * kLn2,
-                                g_cr,
-                                g_cg,
-                                g_cb,
-                                g_w};
-#pragma unroll
-        for (int k = 0; k < 10; ++k)
-            if (vals[k] != 0.f) unsafeAtomicAdd(dst + k, vals[k]);
+        ((float4 *)dst)[0] = make_float4(-(2.f * qa * o.m_x + qb * o.m_y) * kLn2,
+                                         -(qb * o.m_x + 2.f * qc * o.m_y) * kLn2, o.m_xx * kLn2, o.m_xy * kLn2);
+        ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, o.g_cr, o.g_cg);
+        ((float2 *)dst)[4] = make_float2(o.g_cb, o.g_w);
     }
 }
 
@@ -350,7 +374,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // raster backward, per-pixel form (the 3DGS baseline of the paper's ablation): one
 // thread per pixel walks its tile's active entries (staged through LDS like the
 // forward) and adds the 10 screen-space partials of every contributing pair to the
-// splat with one atomic each.  Same partials as k_raster_bwd; kept for comparison.
+// entry's row with one atomic each.  Same partials as k_raster_bwd; kept for
+// comparison.
 // ---------------------------------------------------------------------------------
 template <int S>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(BwdArgs a)
@@ -404,12 +429,13 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
             s_rec[3 * j] = make_float4(x0 - r.a.x, y0 - r.a.y, r.a.z, r.a.w);
             s_rec[3 * j + 1] = r.b;
             s_rec[3 * j + 2] = r.c;
-            s_r[j] = ok ? ri : 0u;
+            s_r[j] = ok ? 1u : 0u;
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
-            float *dst = a.b.sgrad + ((size_t)v * a.b.Acap + s_r[j]) * 10;
+            if (!s_r[j]) continue;
+            float *dst = a.b.ep + (off + base + j) * kEpStride;   // zeroed when the entry was placed
             const float dx = ra.x + colf;
             const float kb = exp_col_b(ra.w, dx), kc = exp_col_c(ra.z, rb.y, dx);
 #pragma unroll
@@ -445,25 +471,44 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
 // largest device (256 CUs); surplus workgroups find the queues drained and exit.
 constexpr unsigned kBwdBlocks = 2048;
 
-bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s)
+template <int S>
+static void launch_bwd_pixel_s(const BwdArgs &a, dim3 block, hipStream_t s, const KTimer *t)
+{
+    const dim3 grid((unsigned)a.b.T);
+    if (t)
+        hipExtLaunchKernelGGL(k_raster_bwd_pixel<S>, grid, block, 0, s, t->start, t->stop, 0, a);
+    else
+        hipLaunchKernelGGL(k_raster_bwd_pixel<S>, grid, block, 0, s, a);
+}
+
+template <int S>
+static void launch_bwd_s(const BwdArgs &a, hipStream_t s, const KTimer *t)
+{
+    const dim3 grid(kBwdBlocks), block(256);
+    if (t)
+        hipExtLaunchKernelGGL(k_raster_bwd<S>, grid, block, 0, s, t->start, t->stop, 0, a);
+    else
+        hipLaunchKernelGGL(k_raster_bwd<S>, grid, block, 0, s, a);
+}
+
+bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s, const KTimer *t)
 {
     (void)rl;
     BwdArgs a{b};
     if (b.T == 0) return true;
     if (b.bwd_mode == OIT_BWD_PER_PIXEL) {
         switch (b.tile) {
-        case 8: hipLaunchKernelGGL(k_raster_bwd_pixel<8>, dim3(b.T), dim3(64), 0, s, a); return true;
-        case 16: hipLaunchKernelGGL(k_raster_bwd_pixel<16>, dim3(b.T), dim3(256), 0, s, a); return true;
-        case 32: hipLaunchKernelGGL(k_raster_bwd_pixel<32>, dim3(b.T), dim3(256), 0, s, a); return true;
+        case 8: launch_bwd_pixel_s<8>(a, dim3(64), s, t); return true;
+        case 16: launch_bwd_pixel_s<16>(a, dim3(256), s, t); return true;
+        case 32: launch_bwd_pixel_s<32>(a, dim3(256), s, t); return true;
         default: return false;
         }
     }
     hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((b.T + 255) / 256)), dim3(256), 0, s, b);
-    const dim3 grid(kBwdBlocks), block(256);
     switch (b.tile) {
-    case 8: hipLaunchKernelGGL(k_raster_bwd<8>, grid, block, 0, s, a); return true;
-    case 16: hipLaunchKernelGGL(k_raster_bwd<16>, grid, block, 0, s, a); return true;
-    case 32: hipLaunchKernelGGL(k_raster_bwd<32>, grid, block, 0, s, a); return true;
+    case 8: launch_bwd_s<8>(a, s, t); return true;
+    case 16: launch_bwd_s<16>(a, s, t); return true;
+    case 32: launch_bwd_s<32>(a, s, t); return true;
     default: return false;
     }
 }
@@ -512,14 +557,35 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t t, int64_t id, int v,
     for (int k = 0; k < 16; ++k) o.Y[k] = 0.f;
     o.gsig = 0.0;
 
-    const float *sg = a.b.sgrad + ((size_t)v * a.b.Acap + t) * 10;
+    // screen-space partials of this (record, view): the sum of its tile entries' rows
     float gs[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gs[k] = 0.f;
+    {
+        const size_t pv = (size_t)v * a.b.Acap + t;
+        const uint64_t cap = (uint64_t)a.b.pair_cap;
+        const uint64_t g0 = a.b.hoff[pv], nh = a.b.nhits[pv];
+        for (uint64_t k = 0; k < nh && g0 + k < cap; ++k) {
+            const uint32_t pos = a.b.rev[g0 + k];
+            if (pos == kNoEntry) continue;
+            const float *e = a.b.ep + (size_t)pos * kEpStride;
+            const float4 e0 = ((const float4 *)e)[0], e1 = ((const float4 *)e)[1];
+            const float2 e2 = ((const float2 *)e)[4];
+            gs[0] += e0.x;
+            gs[1] += e0.y;
+            gs[2] += e0.z;
+            gs[3] += e0.w;
+            gs[4] += e1.x;
+            gs[5] += e1.y;
+            gs[6] += e1.z;
+            gs[7] += e1.w;
+            gs[8] += e2.x;
+            gs[9] += e2.y;
+        }
+    }
     bool any = false;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        gs[k] = sg[k];
-        any |= gs[k] != 0.f;
-    }
+    for (int k = 0; k < 10; ++k) any |= gs[k] != 0.f;
     if (!any) return;
     const CamDev &cam = a.b.cams[v];
     Geo g;

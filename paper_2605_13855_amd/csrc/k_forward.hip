@@ -1,5 +1,7 @@
 // Forward pass: projection, tile binning without depth order, and the per-pixel
 // blend-and-normalise / blend-and-update pass (App. A, Alg. "rasterize").
+#include <hip/hip_ext.h>
+
 #include "oit_internal.h"
 
 namespace oit {
@@ -199,10 +201,14 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
                 const int S = a.b.tile;
                 rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
                 uint32_t *cnt = sign == 0 ? a.b.cnt_a : a.b.cnt_d;
+                uint32_t hits = 0;
                 for (int ty = rect.z; ty < rect.w; ++ty)
                     for (int tx = rect.x; tx < rect.y; ++tx)
-                        if (tile_hit(r, tau, cam, S, tx, ty))
+                        if (tile_hit(r, tau, cam, S, tx, ty)) {
                             atomicAdd(&cnt[cam.tile_base + ty * cam.tiles_x + tx], 1u);
+                            ++hits;
+                        }
+                if (sign == 0) a.b.nhits[(size_t)v * a.rl.Acap + t] = hits;
             }
         }
     } else {
@@ -295,6 +301,97 @@ void launch_scan_tiles(const Buffers &b, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------------
+// device-wide exclusive scan of n uint32 values in three launches: the sum of every
+// block of kScanBlockItems values, an exclusive scan of those sums by one block, and
+// a rescan of each block's values from its offset
+// ---------------------------------------------------------------------------------
+constexpr int kScanPer = kScanBlockItems / 256;   // values per thread
+
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t s_v[256];
+    s_v[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t t = threadIdx.x >= (unsigned)off ? s_v[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s_v[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const uint32_t incl = s_v[threadIdx.x];
+    if (total) *total = s_v[255];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const uint32_t *in, int64_t n, uint32_t *bsum)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanBlockItems;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot = 0;
+    block_excl_scan256(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_block_sums(uint32_t *bsum, int64_t nb)
+{
+    __shared__ uint32_t s_v[kScanThreads];
+    const int tid = threadIdx.x;
+    const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t b0 = (int64_t)tid * seg < nb ? (int64_t)tid * seg : nb;
+    const int64_t b1 = b0 + seg < nb ? b0 + seg : nb;
+    uint32_t acc = 0;
+    for (int64_t i = b0; i < b1; ++i) acc += bsum[i];
+    s_v[tid] = acc;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const uint32_t t = tid >= off ? s_v[tid - off] : 0u;
+        __syncthreads();
+        s_v[tid] += t;
+        __syncthreads();
+    }
+    uint32_t pre = s_v[tid] - acc;
+    for (int64_t i = b0; i < b1; ++i) {
+        const uint32_t x = bsum[i];
+        bsum[i] = pre;
+        pre += x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, int64_t n, const uint32_t *bsum,
+                                                    uint32_t *out)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanBlockItems + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        acc += v[k];
+    }
+    uint32_t pre = block_excl_scan256(acc, nullptr) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = pre;
+        pre += v[k];
+    }
+}
+
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int64_t nb = (n + kScanBlockItems - 1) / kScanBlockItems;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, n, (const uint32_t *)tmp, out);
+}
+
+// ---------------------------------------------------------------------------------
 // emit: place each (tile, record) entry; active entries first within a tile
 // ---------------------------------------------------------------------------------
 struct EmitArgs {
@@ -314,21 +411,33 @@ __device__ void emit_one(const EmitArgs &a, int64_t t, int v)
     const uint64_t cap = (uint64_t)a.b.pair_cap;
     const Rec r = a.b.rec[ri];
     const float tau = tile_tau(r.b.y);
+    // an active pair's k-th tile hit goes to slot k of its gather list (same tile order
+    // as the count in preprocess_one)
+    const uint64_t g0 = sign == 0 ? (uint64_t)a.b.hoff[(size_t)v * a.rl.Acap + t] : 0;
+    const bool zero_ep = sign == 0 && a.b.bwd_mode == OIT_BWD_PER_PIXEL;
+    uint64_t k = 0;
     for (int ty = rect.z; ty < rect.w; ++ty)
         for (int tx = rect.x; tx < rect.y; ++tx) {
             if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
             const int tile = cam.tile_base + ty * cam.tiles_x + tx;
-            uint64_t pos;
+            uint64_t pos = cap;
             if (sign == 0) {
                 const uint32_t slot = atomicAdd(&a.b.fill_a[tile], 1u);
-                if (slot >= a.b.cnt_a[tile]) continue;
-                pos = (uint64_t)a.b.tile_off[tile] + slot;
+                if (slot < a.b.cnt_a[tile]) pos = (uint64_t)a.b.tile_off[tile] + slot;
             } else {
                 const uint32_t slot = atomicAdd(&a.b.fill_d[tile], 1u);
-                if (slot >= a.b.cnt_d[tile]) continue;
-                pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
+                if (slot < a.b.cnt_d[tile]) pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
             }
             if (pos < cap) a.b.entries[pos] = (uint32_t)t;
+            if (sign == 0) {
+                // the gather list has pair_cap slots; a dropped entry is marked
+                if (g0 + k < cap) a.b.rev[g0 + k] = pos < cap ? (uint32_t)pos : kNoEntry;
+                if (pos < cap && zero_ep) {
+                    float4 *e = (float4 *)(a.b.ep + pos * kEpStride);
+                    e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                ++k;
+            }
         }
 }
 
@@ -401,6 +510,30 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
         if (bx <= hx && bx + (float)(BW - 1) >= -hx && by <= hy && by + (float)(BW - 1) >= -hy) mask |= 1 << w;
     }
     return mask;
+}
+
+// Blend one active record into a thread's PPT pixels (BAN accumulators).
+template <int PPT>
+__device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb, const float4 &rc, float cb,
+                                             float cc, const float (&rowf)[PPT], const uint64_t (&inmask)[PPT],
+                                             unsigned long long &npair, float (&P)[PPT][3], float (&Q)[PPT],
+                                             float (&T)[PPT])
+{
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
+        const bool hit = e >= kLog2AlphaMin;
+        npair += (unsigned long long)__builtin_popcountll(__ballot(hit) & inmask[p]);
+        if (hit) {
+            const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+            const float aw = al * rc.y;
+            P[p][0] = fmaf(rb.z, aw, P[p][0]);
+            P[p][1] = fmaf(rb.w, aw, P[p][1]);
+            P[p][2] = fmaf(rc.x, aw, P[p][2]);
+            Q[p] += aw;
+            T[p] *= 1.f - al;
+        }
+    }
 }
 
 // BAU = true: the label-change pass (blend-and-update of the pre-rendered buffer);
@@ -557,21 +690,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
             const float dx = ra.x + colf;
             const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
-#pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
-                const bool hit = e >= kLog2AlphaMin;
-                npair += (unsigned long long)__builtin_popcountll(__ballot(hit) & inmask[p]);
-                if (hit) {
-                    const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
-                    const float aw = al * rc.y;
-                    P[p][0] = fmaf(rb.z, aw, P[p][0]);
-                    P[p][1] = fmaf(rb.w, aw, P[p][1]);
-                    P[p][2] = fmaf(rc.x, aw, P[p][2]);
-                    Q[p] += aw;
-                    T[p] *= 1.f - al;
-                }
-            }
+            blend_active<PPT>(ra, rb, rc, cb, cc, rowf, inmask, npair, P, Q, T);
           }
         }
     }
@@ -623,36 +742,45 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     }
 }
 
+template <typename K>
+static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const KTimer *t, const FwdArgs &a)
+{
+    if (t)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t->start, t->stop, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
+}
+
 template <int S, bool BAU>
-static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s)
+static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
-    case 32: hipLaunchKernelGGL((k_raster_fwd<S, 32, BAU>), grid, block, 0, s, a); return true;
-    case 64: hipLaunchKernelGGL((k_raster_fwd<S, 64, BAU>), grid, block, 0, s, a); return true;
-    case 128: hipLaunchKernelGGL((k_raster_fwd<S, 128, BAU>), grid, block, 0, s, a); return true;
-    case 256: hipLaunchKernelGGL((k_raster_fwd<S, 256, BAU>), grid, block, 0, s, a); return true;
+    case 32: launch_timed(k_raster_fwd<S, 32, BAU>, grid, block, s, t, a); return true;
+    case 64: launch_timed(k_raster_fwd<S, 64, BAU>, grid, block, s, t, a); return true;
+    case 128: launch_timed(k_raster_fwd<S, 128, BAU>, grid, block, s, t, a); return true;
+    case 256: launch_timed(k_raster_fwd<S, 256, BAU>, grid, block, s, t, a); return true;
     default: return false;
     }
 }
 
 template <int S>
-static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s)
+static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s, const KTimer *bau_t, const KTimer *fwd_t)
 {
-    if (a.pre && !raster_fwd_s<S, true>(a, batch, s)) return false;
-    return raster_fwd_s<S, false>(a, batch, s);
+    if (a.pre && !raster_fwd_s<S, true>(a, batch, s, bau_t)) return false;
+    return raster_fwd_s<S, false>(a, batch, s, fwd_t);
 }
 
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s)
+                       float *pixstate, int batch, hipStream_t s, const KTimer *bau_t, const KTimer *fwd_t)
 {
     FwdArgs a{b, sigma, bg[0], bg[1], bg[2], pre, image, pixstate};
     if (b.T == 0) return true;
     switch (b.tile) {
-    case 8: return raster_fwd_both<8>(a, batch, s);
-    case 16: return raster_fwd_both<16>(a, batch, s);
-    case 32: return raster_fwd_both<32>(a, batch, s);
+    case 8: return raster_fwd_both<8>(a, batch, s, bau_t, fwd_t);
+    case 16: return raster_fwd_both<16>(a, batch, s, bau_t, fwd_t);
+    case 32: return raster_fwd_both<32>(a, batch, s, bau_t, fwd_t);
     default: return false;
     }
 }

@@ -15,10 +15,13 @@ namespace {
 
 thread_local char g_err[512] = "";
 
-// optional timing of the two raster kernels (see oit_timing_enable)
-hipEvent_t g_ev[4];
+// optional timing of the raster kernels (see oit_timing_enable): start/stop events of
+// the label-change pass, the active forward pass and the backward
+hipEvent_t g_ev[6];
 bool g_timing_ready = false;
 bool g_timing_on = false;
+bool g_bau_timed = false;   // the last forward launched the label-change pass
+
 
 oit_status fail(oit_status st, const char *fmt, ...)
 {
@@ -35,6 +38,16 @@ oit_status ok()
     return OIT_OK;
 }
 
+// Timing is for eager launches: refuse a capturing stream while it is on.
+oit_status timing_guard(hipStream_t s, const char *what)
+{
+    if (!g_timing_on) return OIT_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return fail(OIT_ERR_INVALID, "%s: kernel timing is on while the stream is being captured", what);
+    return OIT_OK;
+}
+
 oit_status check_launch(const char *what)
 {
     const hipError_t e = hipGetLastError();
@@ -47,8 +60,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
-    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, rec, rect, sgrad, pixconst,
-        pixB, total;
+    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, rec, rect, nhits, hoff, rev,
+        scan_tmp, ep, pixconst, pixB, total;
     uint32_t max_chunks;
     int T;
     int64_t total_px, Acap, Rcap;
@@ -154,7 +167,12 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.entries = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
     p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
     p.rect = o; o = align256(o + sizeof(short4) * (size_t)n_views * p.Rcap);
-    p.sgrad = o; o = align256(o + 4 * 10 * (size_t)n_views * p.Acap);
+    const size_t npairs = (size_t)n_views * p.Acap;
+    p.nhits = o; o = align256(o + 4 * npairs);
+    p.hoff = o; o = align256(o + 4 * npairs);
+    p.scan_tmp = o; o = align256(o + 4 * (npairs / kScanBlockItems + 2));
+    p.rev = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
+    p.ep = o; o = align256(o + 4 * kEpStride * (size_t)tu->pair_capacity);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
     p.total = o;
@@ -179,7 +197,11 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.entries = (uint32_t *)(w + p.entries);
     b.rec = (Rec *)(w + p.rec);
     b.rect = (short4 *)(w + p.rect);
-    b.sgrad = (float *)(w + p.sgrad);
+    b.nhits = (uint32_t *)(w + p.nhits);
+    b.hoff = (uint32_t *)(w + p.hoff);
+    b.scan_tmp = (uint32_t *)(w + p.scan_tmp);
+    b.rev = (uint32_t *)(w + p.rev);
+    b.ep = (float *)(w + p.ep);
     b.pixconst = (float4 *)(w + p.pixconst);
     b.pixB = (float *)(w + p.pixB);
     b.n_views = n_views;
@@ -299,18 +321,22 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     if (ws_bytes < p.total)
         return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
     hipStream_t s = (hipStream_t)stream;
+    if ((st = timing_guard(s, "oit_render_fwd")) != OIT_OK) return st;
     const Buffers b = buffers(p, ws, n_views, tuning);
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.cnt_a, 4 * (size_t)p.T, 0u, s);
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
+    fill_u32(b.nhits, (size_t)n_views * p.Acap, 0u, s);
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
     launch_scan_tiles(b, s);
+    launch_scan_u32(b.nhits, b.hoff, (int64_t)n_views * p.Acap, b.scan_tmp, s);
     launch_emit(rl, b, s);
-    if (g_timing_on) (void)hipEventRecord(g_ev[0], s);
-    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s))
+    const KTimer bau_t{g_ev[0], g_ev[1]}, fwd_t{g_ev[2], g_ev[3]};
+    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s, g_timing_on ? &bau_t : nullptr,
+                           g_timing_on ? &fwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
-    if (g_timing_on) (void)hipEventRecord(g_ev[1], s);
+    if (g_timing_on) g_bau_timed = pre != nullptr;
     return check_launch("oit_render_fwd");
 }
 
@@ -422,18 +448,18 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     if (ws_bytes < p.total)
         return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
     hipStream_t s = (hipStream_t)stream;
+    if ((st = timing_guard(s, "oit_render_bwd")) != OIT_OK) return st;
     const Buffers b = buffers(p, ws, n_views, tuning);
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     const GradPtrs g{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->vsh,
                      grads->stride};
     upload_cams(p.cams_host, n_views, b.cams, s);
-    fill_f32(b.sgrad, 10 * (size_t)n_views * p.Acap, 0.f, s);
     fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
     fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
-    if (g_timing_on) (void)hipEventRecord(g_ev[2], s);
-    if (!launch_raster_bwd(b, rl, s)) return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
-    if (g_timing_on) (void)hipEventRecord(g_ev[3], s);
+    const KTimer bwd_t{g_ev[4], g_ev[5]};
+    if (!launch_raster_bwd(b, rl, s, g_timing_on ? &bwd_t : nullptr))
+        return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
     launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
     return check_launch("oit_render_bwd");
 }
@@ -588,7 +614,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
 oit_status oit_timing_enable(int32_t on)
 {
     if (on && !g_timing_ready) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 6; ++k) {
             const hipError_t e = hipEventCreate(&g_ev[k]);
             if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_timing_enable: %s", hipGetErrorString(e));
         }
@@ -602,11 +628,15 @@ oit_status oit_timing_read(float *out)
 {
     if (!out) return fail(OIT_ERR_INVALID, "oit_timing_read: NULL output");
     if (!g_timing_ready) return fail(OIT_ERR_INVALID, "oit_timing_read: timing was never enabled");
-    for (int k = 0; k < 2; ++k) {
+    float ms[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 3; ++k) {
+        if (k == 0 && !g_bau_timed) continue;
         hipError_t e = hipEventSynchronize(g_ev[2 * k + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&out[k], g_ev[2 * k], g_ev[2 * k + 1]);
-        if (e != hipSuccess) out[k] = -1.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[k], g_ev[2 * k], g_ev[2 * k + 1]);
+        if (e != hipSuccess) ms[k] = -1.f;
     }
+    out[0] = ms[0] < 0.f || ms[1] < 0.f ? -1.f : ms[0] + ms[1];
+    out[1] = ms[2];
     return ok();
 }
 

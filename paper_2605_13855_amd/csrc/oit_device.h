@@ -19,6 +19,9 @@ namespace oit {
 constexpr float kAlphaMax = 0.99f;
 constexpr float kLog2AlphaMax = -0.01449956969511509f;   // log2(0.99)
 constexpr float kLog2AlphaMin = -7.994353436858858f;     // log2(1/255)
+// A splat whose log2 opacity is below kLog2NoCap never reaches the opacity cap: the
+// exponent at any pixel is at most log2(opacity) plus rounding, far below the margin.
+constexpr float kLog2NoCap = kLog2AlphaMax - 1e-4f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kDilation = 0.3f;

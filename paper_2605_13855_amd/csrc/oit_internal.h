@@ -12,6 +12,9 @@ namespace oit {
 constexpr int kMaxViews = 64;
 constexpr int kBwdLanes = 64;   // splats per backward work item (one wave)
 constexpr int kScanThreads = 1024;
+constexpr int kEpStride = 12;                  // floats per entry partial (10 used, 16-byte rows)
+constexpr uint32_t kNoEntry = 0xffffffffu;     // gather-list slot of an entry that was dropped
+constexpr int kScanBlockItems = 256 * 16;      // values per block of the device-wide scan
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
@@ -51,7 +54,12 @@ struct Buffers {
     uint32_t *entries;                          // [pair_cap]
     Rec *rec;                                   // [V][Rcap]
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
-    float *sgrad;                               // [V][Acap][10]
+    // backward gather lists: each active (record, view) pair's tile entries
+    uint32_t *nhits;                            // [V][Acap] tiles the pair reaches
+    uint32_t *hoff;                             // [V][Acap] exclusive scan of nhits
+    uint32_t *rev;                              // [pair_cap] entry positions, by pair
+    uint32_t *scan_tmp;                         // block sums of the scan of nhits
+    float *ep;                                  // [pair_cap][kEpStride] screen-space partials per entry
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
     float *pixB;                                // [total_px] B
     uint32_t max_chunks;
@@ -77,15 +85,23 @@ void fill_f64(double *p, size_t n, double v, hipStream_t s);
 void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const float *sigma, const RowList &rl,
                              const Buffers &b, hipStream_t s);
 void launch_scan_tiles(const Buffers &b, hipStream_t s);
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
 void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s);
+// Optional kernel timing: a launch given a KTimer records `start` when the kernel
+// begins and `stop` when it ends (hipExtLaunchKernelGGL; not for graph capture).
+struct KTimer {
+    hipEvent_t start, stop;
+};
+
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s);
+                       float *pixstate, int batch, hipStream_t s, const KTimer *bau_t = nullptr,
+                       const KTimer *fwd_t = nullptr);
 
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s);
 void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], const float *pre,
                      const float *grad_image, const float *pixstate, double *grad_sigma, hipStream_t s);
-bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s);
+bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s, const KTimer *t = nullptr);
 void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
                            const GradPtrs &g, double *grad_sigma, float *score, const float eps[6],
                            hipStream_t s);
