@@ -74,19 +74,26 @@ def log(msg):
 
 
 def prime(trainer):
-    """First iteration, eager: selection, pair-capacity fit, then the full step."""
+    """First iterations, eager, with the pair capacity fitted before each; returns the
+    largest number of tile entries they needed.  In the active form the first selection
+    moves every splat outside the new active set out of the label set, so that step's
+    tile lists are dense-sized; the second is a steady-state step."""
     from paper_2605_13855_amd import oit
-    if not trainer.dense:
-        trainer.select()
-        trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg, trainer._active(), trainer.pre)
-    else:
-        trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg)
-    trainer.forward_loss()
-    trainer.backward()
-    trainer.optimise()
-    st = trainer.r.status()
-    if st & oit.STATUS_PAIR_OVERFLOW:
-        raise RuntimeError("pair capacity overflow after fitting")
+    need = 0
+    for _ in range(1 if trainer.dense else 2):
+        if not trainer.dense:
+            trainer.select()
+            trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg, trainer._active(), trainer.pre)
+        else:
+            trainer.r.fit_pair_capacity(trainer.params, trainer.sigma, trainer.bg)
+        trainer.forward_loss()
+        trainer.backward()
+        trainer.optimise()
+        need = max(need, trainer.r.pairs_needed())
+        st = trainer.r.status()
+        if st & oit.STATUS_PAIR_OVERFLOW:
+            raise RuntimeError("pair capacity overflow after fitting")
+    return need
 
 
 def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=False):
@@ -116,9 +123,9 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     t = ActiveSetTrainer(scene, fraction=fraction, tile=tile, batch=batch, dense=dense)
     if not dense:
         t.warmup_dense_scores()
-    prime(t)
-    # headroom for the tile lists of later steps (the active set moves)
-    need = t.r.pairs_needed()
+    need = prime(t)
+    # headroom for the tile lists of later steps (the active set moves); the binning's
+    # work follows the entries, not the capacity
     t.r.set_tuning(pair_capacity=min(int(need * 1.5) + 65536, 2 ** 32 - 2))
     log(f"{name}: tile={t.r.tuning.tile} batch={t.r.tuning.batch} pair_capacity={t.r.tuning.pair_capacity}")
     step = t.iteration if eager else t.replay

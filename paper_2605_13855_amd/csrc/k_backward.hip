@@ -151,8 +151,8 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // pixel's constants as a uniform LDS broadcast.  Per splat, the colour and weight
 // sums and the moments of dL/de over the pixel offsets stay in registers; they give
 // the 10 screen-space partials once per work item, stored with plain stores in the
-// entry's own row (no atomics: the preprocess backward gathers a (record, view)
-// pair's rows through its gather list, in a fixed order).
+// entry's own row at its unsorted slot (no atomics: a (record, view) pair's slots are
+// contiguous, and the preprocess backward sums them in a fixed order).
 //
 // The work items are split into 8 contiguous ranges, one per XCD, so that the waves
 // that share a tile's pixel constants share an L2; a wave whose range is drained
@@ -277,8 +277,9 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
             hy = sqrtf(tau * A / det) + 0.01f;
         }
     }
-    // this entry's row of screen-space partials (written for every valid lane)
-    float *dst = b.ep + (off + j) * kEpStride;
+    // this entry's row of screen-space partials, at its unsorted slot (written for every
+    // valid lane)
+    float *dst = b.ep + (size_t)(valid ? b.orig[off + j] : 0u) * kEpStride;
     // bit g: some lane's footprint box reaches group g (pixel offsets [g0, g0 + 7])
     uint32_t mask = 0;
 #pragma unroll
@@ -435,7 +436,8 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
         for (int j = 0; j < cnt; ++j) {
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
             if (!s_r[j]) continue;
-            float *dst = a.b.ep + (off + base + j) * kEpStride;   // zeroed when the entry was placed
+            // the entry's row at its unsorted slot, zeroed when the list was written
+            float *dst = a.b.ep + (size_t)a.b.orig[off + base + j] * kEpStride;
             const float dx = ra.x + colf;
             const float kb = exp_col_b(ra.w, dx), kc = exp_col_c(ra.z, rb.y, dx);
 #pragma unroll
@@ -562,13 +564,12 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t t, int64_t id, int v,
 #pragma unroll
     for (int k = 0; k < 10; ++k) gs[k] = 0.f;
     {
-        const size_t pv = (size_t)v * a.b.Acap + t;
+        // the pair's entries hold the contiguous slots [hoff, hoff + nhits)
+        const size_t pv = (size_t)v * a.b.Rcap + t;
         const uint64_t cap = (uint64_t)a.b.pair_cap;
         const uint64_t g0 = a.b.hoff[pv], nh = a.b.nhits[pv];
         for (uint64_t k = 0; k < nh && g0 + k < cap; ++k) {
-            const uint32_t pos = a.b.rev[g0 + k];
-            if (pos == kNoEntry) continue;
-            const float *e = a.b.ep + (size_t)pos * kEpStride;
+            const float *e = a.b.ep + (g0 + k) * kEpStride;
             const float4 e0 = ((const float4 *)e)[0], e1 = ((const float4 *)e)[1];
             const float2 e2 = ((const float2 *)e)[4];
             gs[0] += e0.x;

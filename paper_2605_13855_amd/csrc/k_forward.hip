@@ -114,7 +114,7 @@ __device__ __forceinline__ int64_t rec_of(const RowList &rl, int64_t na, int64_t
 
 // ---------------------------------------------------------------------------------
 // preprocess: one thread per (listed record, view); projects the splat, writes the
-// record and its tile rectangle and counts the tile entries.
+// record and its tile rectangle and counts the tiles it reaches.
 // ---------------------------------------------------------------------------------
 struct PreArgs {
     SplatPtrs sp;    // active rows
@@ -200,15 +200,11 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
             if (x0 <= x1 && y0 <= y1) {
                 const int S = a.b.tile;
                 rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
-                uint32_t *cnt = sign == 0 ? a.b.cnt_a : a.b.cnt_d;
                 uint32_t hits = 0;
                 for (int ty = rect.z; ty < rect.w; ++ty)
                     for (int tx = rect.x; tx < rect.y; ++tx)
-                        if (tile_hit(r, tau, cam, S, tx, ty)) {
-                            atomicAdd(&cnt[cam.tile_base + ty * cam.tiles_x + tx], 1u);
-                            ++hits;
-                        }
-                if (sign == 0) a.b.nhits[(size_t)v * a.rl.Acap + t] = hits;
+                        if (tile_hit(r, tau, cam, S, tx, ty)) ++hits;
+                a.b.nhits[(size_t)v * a.rl.Rcap + t] = hits;
             }
         }
     } else {
@@ -290,8 +286,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
         b.tile_off[T] = (uint32_t)(te < cap ? te : cap);
         b.chunk_off[T] = (uint32_t)tc;
         b.counters[CNT_TOTAL_CHUNKS] = (uint32_t)tc;
-        b.counters[CNT_TOTAL_ENTRIES] = (uint32_t)(te < 0xffffffffull ? te : 0xffffffffull);
-        if (te > cap) atomicOr(b.status, OIT_STATUS_PAIR_OVERFLOW);
     }
 }
 
@@ -392,56 +386,66 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp
 }
 
 // ---------------------------------------------------------------------------------
-// emit: place each (tile, record) entry; active entries first within a tile
+// Binning without depth order and without atomics (App. A: tiles are the only sort
+// key).  The scan of the per-pair tile counts gives every (record, view) pair its slots
+// [hoff, hoff + nhits) of an unsorted entry list, in pair order; a list pass writes
+// each slot's key (tile, class: active 0, label change 1) and record; a stable LSD radix
+// sort orders the list by key, so that within a tile the active entries come first and
+// both classes keep pair order (the forward's sums are then reproducible run to run);
+// binary searches in the sorted keys give each tile's range.
 // ---------------------------------------------------------------------------------
-struct EmitArgs {
+struct ListArgs {
     RowList rl;
     Buffers b;
+    int64_t npairs;   // views x Rcap
 };
 
-__device__ void emit_one(const EmitArgs &a, int64_t t, int v)
+// total tile entries E, the sorted list's length min(E, capacity), overflow status
+__global__ void k_list_total(ListArgs a)
+{
+    const uint64_t last = (uint64_t)a.npairs - 1;
+    const uint64_t E = (uint64_t)a.b.hoff[last] + a.b.nhits[last];
+    const uint64_t cap = (uint64_t)a.b.pair_cap;
+    a.b.counters[CNT_TOTAL_ENTRIES] = (uint32_t)(E < 0xffffffffull ? E : 0xffffffffull);
+    a.b.counters[CNT_SORT_N] = (uint32_t)(E < cap ? E : cap);
+    if (E > cap) atomicOr(a.b.status, OIT_STATUS_PAIR_OVERFLOW);
+}
+
+__device__ void list_one(const ListArgs &a, int64_t t, int v)
 {
     int sign = 0;
     if (record_row(a.rl, t, sign) < 0) return;
+    const size_t pv = (size_t)v * a.rl.Rcap + t;
+    const uint32_t nh = a.b.nhits[pv];
+    if (nh == 0) return;
     const CamDev &cam = a.b.cams[v];
-    const size_t ri = (size_t)v * a.rl.Rcap + t;
-    const short4 rect = a.b.rect[ri];
-    if (rect.x >= rect.y || rect.z >= rect.w) return;
+    const short4 rect = a.b.rect[pv];
     const int S = a.b.tile;
     const uint64_t cap = (uint64_t)a.b.pair_cap;
-    const Rec r = a.b.rec[ri];
+    const Rec r = a.b.rec[pv];
     const float tau = tile_tau(r.b.y);
-    // an active pair's k-th tile hit goes to slot k of its gather list (same tile order
-    // as the count in preprocess_one)
-    const uint64_t g0 = sign == 0 ? (uint64_t)a.b.hoff[(size_t)v * a.rl.Acap + t] : 0;
+    const uint32_t cls = sign == 0 ? 0u : 1u;
     const bool zero_ep = sign == 0 && a.b.bwd_mode == OIT_BWD_PER_PIXEL;
-    uint64_t k = 0;
+    // the pair's k-th tile hit takes slot hoff + k (same tile order as the count)
+    uint64_t o = a.b.hoff[pv];
     for (int ty = rect.z; ty < rect.w; ++ty)
         for (int tx = rect.x; tx < rect.y; ++tx) {
             if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
-            const int tile = cam.tile_base + ty * cam.tiles_x + tx;
-            uint64_t pos = cap;
-            if (sign == 0) {
-                const uint32_t slot = atomicAdd(&a.b.fill_a[tile], 1u);
-                if (slot < a.b.cnt_a[tile]) pos = (uint64_t)a.b.tile_off[tile] + slot;
-            } else {
-                const uint32_t slot = atomicAdd(&a.b.fill_d[tile], 1u);
-                if (slot < a.b.cnt_d[tile]) pos = (uint64_t)a.b.tile_off[tile] + a.b.cnt_a[tile] + slot;
-            }
-            if (pos < cap) a.b.entries[pos] = (uint32_t)t;
-            if (sign == 0) {
-                // the gather list has pair_cap slots; a dropped entry is marked
-                if (g0 + k < cap) a.b.rev[g0 + k] = pos < cap ? (uint32_t)pos : kNoEntry;
-                if (pos < cap && zero_ep) {
-                    float4 *e = (float4 *)(a.b.ep + pos * kEpStride);
+            if (o < cap) {
+                const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
+                a.b.keys[0][o] = tile * 2u + cls;
+                a.b.vals[0][o] = (uint32_t)o;
+                a.b.rec_of[o] = (uint32_t)t;
+                if (zero_ep) {
+                    float4 *e = (float4 *)(a.b.ep + o * kEpStride);
                     e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                ++k;
             }
+            ++o;
         }
 }
 
-__global__ __launch_bounds__(256) void k_emit(EmitArgs a)
+__global__ __launch_bounds__(256) void k_list(ListArgs a)
 {
     const int V = a.b.n_views;
     const RecItems it = rec_items(a.rl, V);
@@ -451,7 +455,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a)
     int64_t k = i / V;
     int v = (int)(i % V);
     for (; i < it.total; i += stride) {
-        emit_one(a, rec_of(a.rl, it.na, k), v);
+        list_one(a, rec_of(a.rl, it.na, k), v);
         k += sk;
         v += (int)sv;
         if (v >= V) {
@@ -461,10 +465,142 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a)
     }
 }
 
-void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s)
+// --- stable LSD radix sort of (key, value) pairs, 8-bit digits -----------------------
+// A fixed grid of kSortGrid blocks; block b sorts the contiguous range of the n keys
+// (n on the device) that sort_range gives it, so the work follows n, not the capacity,
+// and the block order is the key order (stability).
+__device__ __forceinline__ void sort_range(uint64_t n, uint64_t &lo, uint64_t &hi)
 {
-    EmitArgs a{rl, b};
-    if (rl.Rcap > 0) hipLaunchKernelGGL(k_emit, dim3(kRecBlocks), dim3(256), 0, s, a);
+    uint64_t chunk = (n + kSortGrid - 1) / kSortGrid;
+    chunk = (chunk + 255) & ~255ull;
+    lo = (uint64_t)blockIdx.x * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+    if (lo > hi) lo = hi;
+}
+
+// digit histogram of each block's range, digit-major: hist[d][block]
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const uint32_t *nptr, int shift,
+                                                    uint32_t *hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t lo, hi;
+    sort_range(*nptr, lo, hi);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[(size_t)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter each block's keys to their digit's range in key order: rounds of 256 keys in
+// index order; within a round a key's rank among equal digits comes from ballots over
+// the digit's bits (in-wave) and the per-wave counts of lower waves (LDS).
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                       uint32_t *keys_out, uint32_t *vals_out, const uint32_t *nptr,
+                                                       int shift, const uint32_t *hist_off)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
+    for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    uint64_t lo, hi;
+    sort_range(*nptr, lo, hi);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint64_t base = lo; base < hi; base += 256) {
+        const uint64_t i = base + tid;
+        const bool valid = i < hi;
+        const uint32_t key = valid ? keys_in[i] : 0u, val = valid ? vals_in[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(set);
+            peers &= set ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__builtin_popcountll(peers & lt);
+        if (valid && rank == 0) wc[wave][d] = (uint32_t)__builtin_popcountll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wc[w][d];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+        __syncthreads();
+    }
+}
+
+// sorted entry p: its record and its unsorted slot
+__global__ __launch_bounds__(256) void k_finalize(const uint32_t *vals, const uint32_t *rec_of, const uint32_t *nptr,
+                                                  uint32_t *entries, uint32_t *orig, uint64_t cap)
+{
+    const uint64_t n = *nptr;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n && p < cap; p += stride) {
+        const uint32_t o = vals[p];
+        orig[p] = o;
+        entries[p] = rec_of[o];
+    }
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t n, uint32_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// per-tile entry counts from the sorted keys
+__global__ __launch_bounds__(256) void k_tile_counts(const uint32_t *keys, const uint32_t *nptr, Buffers b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.T) return;
+    const uint32_t n = *nptr;
+    const uint32_t s0 = lower_bound_u32(keys, n, 2u * t), s1 = lower_bound_u32(keys, n, 2u * t + 1u),
+                   s2 = lower_bound_u32(keys, n, 2u * t + 2u);
+    b.cnt_a[t] = s1 - s0;
+    b.cnt_d[t] = s2 - s1;
+}
+
+void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
+{
+    const int64_t npairs = (int64_t)b.n_views * rl.Rcap;
+    if (npairs <= 0) return;
+    launch_scan_u32(b.nhits, b.hoff, npairs, b.scan_tmp, s);
+    ListArgs la{rl, b, npairs};
+    hipLaunchKernelGGL(k_list_total, dim3(1), dim3(1), 0, s, la);
+    hipLaunchKernelGGL(k_list, dim3(kRecBlocks), dim3(256), 0, s, la);
+    // keys are tile * 2 + class < 2 T: as many 8-bit digits as that needs
+    const uint32_t kmax = 2u * (uint32_t)b.T;
+    int bits = 0;
+    while (bits < 32 && (kmax >> bits) != 0) ++bits;
+    const int passes = bits == 0 ? 0 : (bits + 7) / 8;
+    const uint32_t *nptr = b.counters + CNT_SORT_N;
+    int cur = 0;
+    for (int ps = 0; ps < passes; ++ps) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur], nptr, 8 * ps,
+                           b.hist);
+        launch_scan_u32(b.hist, b.hist_off, 256 * (int64_t)kSortGrid, b.scan_tmp, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur],
+                           (const uint32_t *)b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], nptr, 8 * ps,
+                           (const uint32_t *)b.hist_off);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(kRecBlocks), dim3(256), 0, s, (const uint32_t *)b.vals[cur],
+                       (const uint32_t *)b.rec_of, nptr, b.entries, b.orig, (uint64_t)b.pair_cap);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((b.T + 255) / 256)), dim3(256), 0, s,
+                       (const uint32_t *)b.keys[cur], nptr, b);
+    launch_scan_tiles(b, s);
 }
 
 // ---------------------------------------------------------------------------------

@@ -60,8 +60,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
-    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, rec, rect, nhits, hoff, rev,
-        scan_tmp, ep, pixconst, pixB, total;
+    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, orig, keys0, keys1, vals0,
+        vals1, rec_of, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, total;
     uint32_t max_chunks;
     int T;
     int64_t total_px, Acap, Rcap;
@@ -157,22 +157,31 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.status = o; o = align256(o + 4);
     p.cams = o; o = align256(o + sizeof(CamDev) * kMaxViews);
     p.counters = o; o = align256(o + 4 * CNT_SLOTS);
-    p.tiles = o; o = align256(o + 4 * 4 * (size_t)p.T);
+    p.tiles = o; o = align256(o + 4 * 2 * (size_t)p.T);
     p.tile_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
     p.chunk_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
     // every tile adds at most one partial chunk to the pair capacity's full ones
     const uint64_t mc = (uint64_t)tu->pair_capacity / kBwdLanes + (uint64_t)p.T + 1;
     p.max_chunks = (uint32_t)(mc < 0xffffffffull ? mc : 0xffffffffull);
     p.chunk_tile = o; o = align256(o + 4 * (size_t)p.max_chunks);
-    p.entries = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
+    const size_t pc = (size_t)tu->pair_capacity;
+    p.entries = o; o = align256(o + 4 * pc);
+    p.orig = o; o = align256(o + 4 * pc);
+    p.keys0 = o; o = align256(o + 4 * pc);
+    p.keys1 = o; o = align256(o + 4 * pc);
+    p.vals0 = o; o = align256(o + 4 * pc);
+    p.vals1 = o; o = align256(o + 4 * pc);
+    p.rec_of = o; o = align256(o + 4 * pc);
+    p.hist = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
+    p.hist_off = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
     p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
     p.rect = o; o = align256(o + sizeof(short4) * (size_t)n_views * p.Rcap);
-    const size_t npairs = (size_t)n_views * p.Acap;
+    const size_t npairs = (size_t)n_views * p.Rcap;
     p.nhits = o; o = align256(o + 4 * npairs);
     p.hoff = o; o = align256(o + 4 * npairs);
-    p.scan_tmp = o; o = align256(o + 4 * (npairs / kScanBlockItems + 2));
-    p.rev = o; o = align256(o + 4 * (size_t)tu->pair_capacity);
-    p.ep = o; o = align256(o + 4 * kEpStride * (size_t)tu->pair_capacity);
+    const size_t nscan = npairs > 256 * (size_t)kSortGrid ? npairs : 256 * (size_t)kSortGrid;
+    p.scan_tmp = o; o = align256(o + 4 * (nscan / kScanBlockItems + 2));
+    p.ep = o; o = align256(o + 4 * kEpStride * pc);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
     p.total = o;
@@ -188,19 +197,24 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.counters = (uint32_t *)(w + p.counters);
     b.cnt_a = (uint32_t *)(w + p.tiles);
     b.cnt_d = b.cnt_a + p.T;
-    b.fill_a = b.cnt_d + p.T;
-    b.fill_d = b.fill_a + p.T;
     b.tile_off = (uint32_t *)(w + p.tile_off);
     b.chunk_off = (uint32_t *)(w + p.chunk_off);
     b.chunk_tile = (uint32_t *)(w + p.chunk_tile);
     b.max_chunks = p.max_chunks;
     b.entries = (uint32_t *)(w + p.entries);
+    b.orig = (uint32_t *)(w + p.orig);
+    b.keys[0] = (uint32_t *)(w + p.keys0);
+    b.keys[1] = (uint32_t *)(w + p.keys1);
+    b.vals[0] = (uint32_t *)(w + p.vals0);
+    b.vals[1] = (uint32_t *)(w + p.vals1);
+    b.rec_of = (uint32_t *)(w + p.rec_of);
+    b.hist = (uint32_t *)(w + p.hist);
+    b.hist_off = (uint32_t *)(w + p.hist_off);
     b.rec = (Rec *)(w + p.rec);
     b.rect = (short4 *)(w + p.rect);
     b.nhits = (uint32_t *)(w + p.nhits);
     b.hoff = (uint32_t *)(w + p.hoff);
     b.scan_tmp = (uint32_t *)(w + p.scan_tmp);
-    b.rev = (uint32_t *)(w + p.rev);
     b.ep = (float *)(w + p.ep);
     b.pixconst = (float4 *)(w + p.pixconst);
     b.pixB = (float *)(w + p.pixB);
@@ -325,13 +339,10 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     const Buffers b = buffers(p, ws, n_views, tuning);
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
-    fill_u32(b.cnt_a, 4 * (size_t)p.T, 0u, s);
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
-    fill_u32(b.nhits, (size_t)n_views * p.Acap, 0u, s);
+    fill_u32(b.nhits, (size_t)n_views * p.Rcap, 0u, s);
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
-    launch_scan_tiles(b, s);
-    launch_scan_u32(b.nhits, b.hoff, (int64_t)n_views * p.Acap, b.scan_tmp, s);
-    launch_emit(rl, b, s);
+    launch_binning(rl, b, s);
     const KTimer bau_t{g_ev[0], g_ev[1]}, fwd_t{g_ev[2], g_ev[3]};
     if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s, g_timing_on ? &bau_t : nullptr,
                            g_timing_on ? &fwd_t : nullptr))

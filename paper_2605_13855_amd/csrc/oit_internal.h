@@ -13,13 +13,15 @@ constexpr int kMaxViews = 64;
 constexpr int kBwdLanes = 64;   // splats per backward work item (one wave)
 constexpr int kScanThreads = 1024;
 constexpr int kEpStride = 12;                  // floats per entry partial (10 used, 16-byte rows)
-constexpr uint32_t kNoEntry = 0xffffffffu;     // gather-list slot of an entry that was dropped
 constexpr int kScanBlockItems = 256 * 16;      // values per block of the device-wide scan
+constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (each a contiguous range)
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
 // CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue counters
-enum { CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8, CNT_SLOTS = 16 };
+// CNT_SORT_N: tile entries that fit the pair capacity (the sorted list's length)
+enum { CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
+       CNT_SLOTS = 16 };
 constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
 struct SplatPtrs {
@@ -48,18 +50,23 @@ struct Buffers {
     int32_t *status;
     CamDev *cams;
     uint32_t *counters;
-    uint32_t *cnt_a, *cnt_d, *fill_a, *fill_d;  // [T]
+    uint32_t *cnt_a, *cnt_d;                    // [T] active / label-change entries per tile
     uint32_t *tile_off, *chunk_off;             // [T + 1]
     uint32_t *chunk_tile;                       // [max_chunks] tile of each backward work item
+    // Tile entries.  Every (record, view) pair owns the slots [hoff, hoff + nhits) of the
+    // unsorted list, one per tile it reaches; the list is sorted by (tile, class) into
+    // `entries` (record index) and `orig` (the entry's unsorted slot).
     uint32_t *entries;                          // [pair_cap]
+    uint32_t *orig;                             // [pair_cap]
+    uint32_t *keys[2], *vals[2];                // [pair_cap] radix-sort buffers
+    uint32_t *rec_of;                           // [pair_cap] record of each unsorted slot
+    uint32_t *hist, *hist_off;                  // [256][kSortGrid] digit counts and their scan
     Rec *rec;                                   // [V][Rcap]
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
-    // backward gather lists: each active (record, view) pair's tile entries
-    uint32_t *nhits;                            // [V][Acap] tiles the pair reaches
-    uint32_t *hoff;                             // [V][Acap] exclusive scan of nhits
-    uint32_t *rev;                              // [pair_cap] entry positions, by pair
-    uint32_t *scan_tmp;                         // block sums of the scan of nhits
-    float *ep;                                  // [pair_cap][kEpStride] screen-space partials per entry
+    uint32_t *nhits;                            // [V][Rcap] tiles the (record, view) pair reaches
+    uint32_t *hoff;                             // [V][Rcap] exclusive scan of nhits
+    uint32_t *scan_tmp;                         // block sums of the device-wide scans
+    float *ep;                                  // [pair_cap][kEpStride] screen-space partials, by unsorted slot
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
     float *pixB;                                // [total_px] B
     uint32_t max_chunks;
@@ -84,9 +91,9 @@ void fill_f64(double *p, size_t n, double v, hipStream_t s);
 
 void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const float *sigma, const RowList &rl,
                              const Buffers &b, hipStream_t s);
-void launch_scan_tiles(const Buffers &b, hipStream_t s);
 void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
-void launch_emit(const RowList &rl, const Buffers &b, hipStream_t s);
+// count scan, entry list, sort by (tile, class), per-tile ranges (after preprocess)
+void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s);
 // Optional kernel timing: a launch given a KTimer records `start` when the kernel
 // begins and `stop` when it ends (hipExtLaunchKernelGGL; not for graph capture).
 struct KTimer {
