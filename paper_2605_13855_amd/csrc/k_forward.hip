@@ -445,23 +445,18 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v)
         }
 }
 
+// view-major items: consecutive lanes take consecutive records of one view, whose
+// slots are adjacent in the unsorted list
 __global__ __launch_bounds__(256) void k_list(ListArgs a)
 {
     const int V = a.b.n_views;
     const RecItems it = rec_items(a.rl, V);
+    const int64_t nrec = it.total / (V > 0 ? V : 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t sk = stride / V, sv = stride % V;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t k = i / V;
-    int v = (int)(i % V);
-    for (; i < it.total; i += stride) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < it.total; i += stride) {
+        const int v = (int)(i / nrec);
+        const int64_t k = i - (int64_t)v * nrec;
         list_one(a, rec_of(a.rl, it.na, k), v);
-        k += sk;
-        v += (int)sv;
-        if (v >= V) {
-            v -= V;
-            ++k;
-        }
     }
 }
 
@@ -648,6 +643,49 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
     return mask;
 }
 
+// Blend-and-update one label-change record (staged at r) into a thread's PPT pixels:
+// sign-weighted, sigma-free sums (sign * alpha * v and the same times d, by colour),
+// and the factors (1 - alpha) into the product T of the record's sign.
+template <int PPT>
+__device__ __forceinline__ void bau_record(const float4 *r, float colf, const float (&rowf)[PPT], float sign,
+                                           float (&dP0)[PPT][3], float (&dP1)[PPT][3], float (&dQ0)[PPT],
+                                           float (&dQ1)[PPT], float (&T)[PPT])
+{
+    const float4 ra = r[0], rb = r[1], rc = r[2];
+    const float dx = ra.x + colf;
+    const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
+    const float sv = sign * rc.y;   // sign * v
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
+        if (e >= kLog2AlphaMin) {
+            const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+            const float sav = al * sv;        // sign * alpha * v
+            const float savd = sav * rc.z;    // ... * d
+            dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
+            dP0[p][1] = fmaf(rb.w, sav, dP0[p][1]);
+            dP0[p][2] = fmaf(rc.x, sav, dP0[p][2]);
+            dP1[p][0] = fmaf(rb.z, savd, dP1[p][0]);
+            dP1[p][1] = fmaf(rb.w, savd, dP1[p][1]);
+            dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
+            dQ0[p] += sav;
+            dQ1[p] += savd;
+            T[p] *= 1.f - al;
+        }
+    }
+}
+
+// log T changes by ln Tp - ln Tm; the products restart at 1
+template <int PPT>
+__device__ __forceinline__ void fold_log_t(float (&dL)[PPT], float (&Tp)[PPT], float (&Tm)[PPT])
+{
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        dL[p] += (__builtin_amdgcn_logf(Tp[p]) - __builtin_amdgcn_logf(Tm[p])) * kLn2;
+        Tp[p] = Tm[p] = 1.f;
+    }
+}
+
 // Blend one active record into a thread's PPT pixels (BAN accumulators).
 template <int PPT>
 __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb, const float4 &rc, float cb,
@@ -741,53 +779,38 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
             __syncthreads();
             for (int j = threadIdx.x; j < cnt; j += NT) {
                 const uint32_t ri = a.b.entries[off + na + base + j];
-                s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j],
-                                                   (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec, x0, y0);
+                const Rec r = (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec;
+                // bit 8: the record leaves the pre-rendered set's complement (sign -1)
+                s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j], r, x0, y0) | (r.c.w < 0.f ? 0x100 : 0);
             }
             __syncthreads();
             for (int sb = 0; sb < cnt; sb += 64) {
-              // the staged records that reach this wave's block, one bit each
-              uint64_t todo = __ballot(sb + lane < cnt && (s_mask[sb + lane] & wbit));
-              while (todo) {
-                const int j = sb + (int)__builtin_ctzll(todo);
-                todo &= todo - 1;
-                const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
-                const float dx = ra.x + colf;
-                const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
-#pragma unroll
-                for (int p = 0; p < PPT; ++p) {
-                    const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
-                    if (e >= kLog2AlphaMin) {
-                        const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
-                        const float sav = rc.w * al * rc.y;       // sign * alpha * v
-                        const float savd = sav * rc.z;            // ... * d
-                        dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
-                        dP0[p][1] = fmaf(rb.w, sav, dP0[p][1]);
-                        dP0[p][2] = fmaf(rc.x, sav, dP0[p][2]);
-                        dP1[p][0] = fmaf(rb.z, savd, dP1[p][0]);
-                        dP1[p][1] = fmaf(rb.w, savd, dP1[p][1]);
-                        dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
-                        dQ0[p] += sav;
-                        dQ1[p] += savd;
-                        if (rc.w > 0.f)
-                            Tp[p] *= 1.f - al;
-                        else
-                            Tm[p] *= 1.f - al;
-                    }
-                }
+              // the staged records that reach this wave's block, one bit each, by sign
+              const int m = sb + lane < cnt ? s_mask[sb + lane] : 0;
+              const bool mine = (m & wbit) != 0;
+              uint64_t todo_p = __ballot(mine && !(m & 0x100)), todo_m = __ballot(mine && (m & 0x100));
+              // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
+              while (todo_p) {
+                const int j = sb + (int)__builtin_ctzll(todo_p);
+                todo_p &= todo_p - 1;
+                bau_record<PPT>(s_rec + 3 * j, colf, rowf, 1.f, dP0, dP1, dQ0, dQ1, Tp);
                 if (++since_fold == kFold) {
                     since_fold = 0;
-#pragma unroll
-                    for (int p = 0; p < PPT; ++p) {
-                        dL[p] += (__builtin_amdgcn_logf(Tp[p]) - __builtin_amdgcn_logf(Tm[p])) * kLn2;
-                        Tp[p] = Tm[p] = 1.f;
-                    }
+                    fold_log_t<PPT>(dL, Tp, Tm);
+                }
+              }
+              while (todo_m) {
+                const int j = sb + (int)__builtin_ctzll(todo_m);
+                todo_m &= todo_m - 1;
+                bau_record<PPT>(s_rec + 3 * j, colf, rowf, -1.f, dP0, dP1, dQ0, dQ1, Tm);
+                if (++since_fold == kFold) {
+                    since_fold = 0;
+                    fold_log_t<PPT>(dL, Tp, Tm);
                 }
               }
             }
         }
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) dL[p] += (__builtin_amdgcn_logf(Tp[p]) - __builtin_amdgcn_logf(Tm[p])) * kLn2;
+        fold_log_t<PPT>(dL, Tp, Tm);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (!in[p]) continue;

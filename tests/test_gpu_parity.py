@@ -365,6 +365,33 @@ def test_pair_overflow_is_reported_and_bounded():
     assert r.status() == 0
 
 
+def test_forward_and_backward_are_run_to_run_reproducible():
+    """The tile lists come from a stable sort and the backward has no atomics: two calls
+    on the same inputs give bitwise equal images, states and gradients."""
+    sc = scenes.make_scene(2)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n, tile=32, batch=64)
+    r.fit_pair_capacity(params, sigma, sc.background)
+    rng = np.random.default_rng(3)
+    gimg = r.pack([rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cameras])
+    outs = []
+    for _ in range(2):
+        r.forward(params, sigma, sc.background)
+        g = new_grads(sc.n, DEV)
+        gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+        r.backward(params, sigma, sc.background, gimg, g, gsig)
+        torch.cuda.synchronize()
+        outs.append((r.image.clone(), r.pixstate.clone(), {k: v.clone() for k, v in g.items()}, gsig.clone()))
+    assert r.status() == 0
+    (i0, s0, g0, q0), (i1, s1, g1, q1) = outs
+    assert torch.equal(i0, i1) and torch.equal(s0, s1)
+    for k in g0:
+        assert torch.equal(g0[k], g1[k]), k
+    # sigma sums FP64 block partials with one atomic per block: equal to rounding
+    assert abs(float(q0.item()) - float(q1.item())) <= 1e-12 * max(1.0, abs(float(q0.item())))
+
+
 def test_autograd_matches_oracle_finite_differences():
     """OITRender's backward against FP64 central differences of the oracle forward."""
     log("autograd vs oracle finite differences")
