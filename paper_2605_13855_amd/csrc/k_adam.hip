@@ -22,6 +22,14 @@ __device__ __constant__ const int kGroupStart[7] = {0, 3, 6, 10, 11, 59, 75};
 // grid.y = component (75), grid.x covers the active rows
 __global__ __launch_bounds__(256) void k_sparse_adam(AdamArgs a)
 {
+    // bias corrections of this step, once per block
+    __shared__ float s_bc[2];
+    if (threadIdx.x == 0) {
+        const float t = (float)*a.step;
+        s_bc[0] = 1.f - powf(a.b1, t);
+        s_bc[1] = 1.f - powf(a.b2, t);
+    }
+    __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t na = a.n_active ? (int64_t)*a.n_active : a.n;
     if (r >= na) return;
@@ -34,8 +42,7 @@ __global__ __launch_bounds__(256) void k_sparse_adam(AdamArgs a)
     const int64_t id = a.idx ? (int64_t)a.idx[r] : r;
     const size_t pi = (size_t)sub * a.n + id;
     const float g = a.p.g[grp][(size_t)sub * a.gstride + r];
-    const float t = (float)*a.step;
-    const float bc1 = 1.f - powf(a.b1, t), bc2 = 1.f - powf(a.b2, t);
+    const float bc1 = s_bc[0], bc2 = s_bc[1];
     const float m = a.b1 * a.p.m[grp][pi] + (1.f - a.b1) * g;
     const float v = a.b2 * a.p.v[grp][pi] + (1.f - a.b2) * g * g;
     a.p.m[grp][pi] = m;

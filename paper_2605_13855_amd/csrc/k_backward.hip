@@ -124,13 +124,16 @@ __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
         if (a.pre) {
             const float *pr = a.pre + 9 * pb + local;
             const float Q1 = pr[7 * HW];
-            const double sig = (double)*a.sigma;
-            acc += ((double)A0 * ((double)pr[3 * HW] - (double)F[0] * Q1) +
+            // numerator of sum_ch A_ch (P1_ch - F_ch Q1) / sigma^2; divided once below
+            acc += (double)A0 * ((double)pr[3 * HW] - (double)F[0] * Q1) +
                    (double)A1 * ((double)pr[4 * HW] - (double)F[1] * Q1) +
-                   (double)A2 * ((double)pr[5 * HW] - (double)F[2] * Q1)) / (sig * sig);
+                   (double)A2 * ((double)pr[5 * HW] - (double)F[2] * Q1);
         }
     }
-    if (a.pre) block_add_double(acc, a.grad_sigma);
+    if (a.pre) {
+        const double sig = (double)*a.sigma;
+        block_add_double(acc / (sig * sig), a.grad_sigma);
+    }
 }
 
 void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], const float *pre,
@@ -544,7 +547,7 @@ struct ViewPart {
 
 // Chain rule of one view, from the record's 10 screen-space partials to the splat's
 // parameters (Sec. 3.1 model; the inverse of the forward projection step by step).
-__device__ void view_partials(const PreBwdArgs &a, int64_t t, int64_t id, int v, const float mu[3],
+__device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int64_t id, int v, const float mu[3],
                               const float S6[6], float sigma, ViewPart &o)
 {
     const int64_t n = a.sp.n;
@@ -564,8 +567,9 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t t, int64_t id, int v,
 #pragma unroll
     for (int k = 0; k < 10; ++k) gs[k] = 0.f;
     {
-        // the pair's entries hold the contiguous slots [hoff, hoff + nhits)
-        const size_t pv = (size_t)v * a.b.Rcap + t;
+        // the pair's entries hold the contiguous slots [hoff, hoff + nhits); active rows
+        // are the first listed records, so the pair index is view * nrec + t
+        const size_t pv = (size_t)v * nrec + t;
         const uint64_t cap = (uint64_t)a.b.pair_cap;
         const uint64_t g0 = a.b.hoff[pv], nh = a.b.nhits[pv];
         for (uint64_t k = 0; k < nh && g0 + k < cap; ++k) {
@@ -723,6 +727,9 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
     const int64_t st = a.g.stride;
     int64_t na = a.rl.n_active ? (int64_t)*a.rl.n_active : a.rl.n_active_host;
     na = na < 0 ? 0 : (na > a.rl.Acap ? a.rl.Acap : na);
+    int64_t nd = a.rl.n_delta ? (int64_t)*a.rl.n_delta : 0;
+    nd = nd < 0 ? 0 : (nd > a.rl.Rcap - a.rl.Acap ? a.rl.Rcap - a.rl.Acap : nd);
+    const int64_t nrec = na + nd;   // listed records: pair index = view * nrec + listed index
     const float sigma = *a.sigma;
     double gsig = 0.0;
 
@@ -750,7 +757,7 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
         {
             ViewPart o;
             if (row_ok && vl < V) {
-                view_partials(a, t, id, vl, mu, S6, sigma, o);
+                view_partials(a, nrec, t, id, vl, mu, S6, sigma, o);
             } else {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) o.g_mu[k] = 0.f;

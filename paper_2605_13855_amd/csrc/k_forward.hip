@@ -93,7 +93,7 @@ __device__ __forceinline__ bool tile_hit(const Rec &r, float tau, const CamDev &
 constexpr unsigned kRecBlocks = 2048;
 
 struct RecItems {
-    int64_t na, total;   // listed active rows; items = (na + n_delta) * views
+    int64_t na, nrec, total;   // listed active rows; listed records (na + n_delta); items = nrec * views
 };
 
 __device__ __forceinline__ RecItems rec_items(const RowList &rl, int n_views)
@@ -103,7 +103,7 @@ __device__ __forceinline__ RecItems rec_items(const RowList &rl, int n_views)
     int64_t nd = rl.n_delta ? (int64_t)*rl.n_delta : 0;
     const int64_t dcap = rl.Rcap - rl.Acap;
     nd = nd < 0 ? 0 : (nd > dcap ? dcap : nd);
-    return RecItems{na, (na + nd) * n_views};
+    return RecItems{na, na + nd, (na + nd) * n_views};
 }
 
 // record index of listed record k (active rows first, then label changes)
@@ -124,7 +124,8 @@ struct PreArgs {
     Buffers b;
 };
 
-__device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
+// t: record index; pv: the (listed record, view) pair's index view * nrec + k
+__device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
 {
     int sign = 0;
     const int64_t id = record_row(a.rl, t, sign);
@@ -149,6 +150,7 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
 
     Rec r;
     short4 rect = make_short4(0, 0, 0, 0);
+    uint32_t hits = 0;
     Geo g;
     if (geometry(cam, mu, S6, g)) {
         const float lo = -log2f(1.f + expf(-sp.logit[id]));   // log2(sigmoid(logit))
@@ -200,11 +202,9 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
             if (x0 <= x1 && y0 <= y1) {
                 const int S = a.b.tile;
                 rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
-                uint32_t hits = 0;
                 for (int ty = rect.z; ty < rect.w; ++ty)
                     for (int tx = rect.x; tx < rect.y; ++tx)
                         if (tile_hit(r, tau, cam, S, tx, ty)) ++hits;
-                a.b.nhits[(size_t)v * a.rl.Rcap + t] = hits;
             }
         }
     } else {
@@ -214,6 +214,7 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v)
     }
     a.b.rec[ri] = r;
     a.b.rect[ri] = rect;
+    a.b.nhits[pv] = hits;
 }
 
 __global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
     int64_t k = i / V;
     int v = (int)(i % V);
     for (; i < it.total; i += stride) {
-        preprocess_one(a, rec_of(a.rl, it.na, k), v);
+        preprocess_one(a, rec_of(a.rl, it.na, k), v, (size_t)v * it.nrec + k);
         k += sk;
         v += (int)sv;
         if (v >= V) {
@@ -376,6 +377,63 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, int64_t 
     }
 }
 
+// the same scan for a count that lives on the device: a fixed grid of kScanGrid blocks,
+// each scanning a contiguous range of whole kScanBlockItems tiles
+constexpr unsigned kScanGrid = 1024;
+
+__device__ __forceinline__ void scan_range(uint64_t n, uint64_t &lo, uint64_t &hi)
+{
+    uint64_t chunk = (n + kScanGrid - 1) / kScanGrid;
+    chunk = (chunk + kScanBlockItems - 1) / kScanBlockItems * kScanBlockItems;
+    lo = (uint64_t)blockIdx.x * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+    if (lo > hi) lo = hi;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums_dev(const uint32_t *in, const uint32_t *nptr, uint32_t *bsum)
+{
+    uint64_t lo, hi;
+    scan_range(*nptr, lo, hi);
+    uint32_t acc = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) acc += in[i];
+    uint32_t tot = 0;
+    block_excl_scan256(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply_dev(const uint32_t *in, const uint32_t *nptr,
+                                                        const uint32_t *bsum, uint32_t *out)
+{
+    uint64_t lo, hi;
+    scan_range(*nptr, lo, hi);
+    uint32_t carry = bsum[blockIdx.x];
+    for (uint64_t base = lo; base < hi; base += kScanBlockItems) {
+        const uint64_t t0 = base + (uint64_t)threadIdx.x * kScanPer;
+        uint32_t v[kScanPer];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = t0 + k < hi ? in[t0 + k] : 0u;
+            acc += v[k];
+        }
+        uint32_t tot = 0;
+        uint32_t pre = block_excl_scan256(acc, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (t0 + k < hi) out[t0 + k] = pre;
+            pre += v[k];
+        }
+        carry += tot;
+    }
+}
+
+void launch_scan_u32_dev(const uint32_t *in, uint32_t *out, const uint32_t *nptr, uint32_t *tmp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_sums_dev, dim3(kScanGrid), dim3(256), 0, s, in, nptr, tmp);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, (int64_t)kScanGrid);
+    hipLaunchKernelGGL(k_scan_apply_dev, dim3(kScanGrid), dim3(256), 0, s, in, nptr, (const uint32_t *)tmp, out);
+}
+
 void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s)
 {
     if (n <= 0) return;
@@ -397,32 +455,38 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp
 struct ListArgs {
     RowList rl;
     Buffers b;
-    int64_t npairs;   // views x Rcap
 };
+
+// number of (listed record, view) pairs of the call, for the scan of their tile counts
+__global__ void k_pair_count(ListArgs a)
+{
+    const RecItems it = rec_items(a.rl, a.b.n_views);
+    a.b.counters[CNT_NPAIRS] = (uint32_t)it.total;
+}
 
 // total tile entries E, the sorted list's length min(E, capacity), overflow status
 __global__ void k_list_total(ListArgs a)
 {
-    const uint64_t last = (uint64_t)a.npairs - 1;
-    const uint64_t E = (uint64_t)a.b.hoff[last] + a.b.nhits[last];
+    const uint32_t np = a.b.counters[CNT_NPAIRS];
+    const uint64_t E = np ? (uint64_t)a.b.hoff[np - 1] + a.b.nhits[np - 1] : 0;
     const uint64_t cap = (uint64_t)a.b.pair_cap;
     a.b.counters[CNT_TOTAL_ENTRIES] = (uint32_t)(E < 0xffffffffull ? E : 0xffffffffull);
     a.b.counters[CNT_SORT_N] = (uint32_t)(E < cap ? E : cap);
     if (E > cap) atomicOr(a.b.status, OIT_STATUS_PAIR_OVERFLOW);
 }
 
-__device__ void list_one(const ListArgs &a, int64_t t, int v)
+__device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
 {
     int sign = 0;
     if (record_row(a.rl, t, sign) < 0) return;
-    const size_t pv = (size_t)v * a.rl.Rcap + t;
     const uint32_t nh = a.b.nhits[pv];
     if (nh == 0) return;
     const CamDev &cam = a.b.cams[v];
-    const short4 rect = a.b.rect[pv];
+    const size_t ri = (size_t)v * a.rl.Rcap + t;
+    const short4 rect = a.b.rect[ri];
     const int S = a.b.tile;
     const uint64_t cap = (uint64_t)a.b.pair_cap;
-    const Rec r = a.b.rec[pv];
+    const Rec r = a.b.rec[ri];
     const float tau = tile_tau(r.b.y);
     const uint32_t cls = sign == 0 ? 0u : 1u;
     const bool zero_ep = sign == 0 && a.b.bwd_mode == OIT_BWD_PER_PIXEL;
@@ -435,7 +499,7 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v)
                 const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
                 a.b.keys[0][o] = tile * 2u + cls;
                 a.b.vals[0][o] = (uint32_t)o;
-                a.b.rec_of[o] = (uint32_t)t;
+                a.b.recs[0][o] = (uint32_t)t;
                 if (zero_ep) {
                     float4 *e = (float4 *)(a.b.ep + o * kEpStride);
                     e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -451,12 +515,11 @@ __global__ __launch_bounds__(256) void k_list(ListArgs a)
 {
     const int V = a.b.n_views;
     const RecItems it = rec_items(a.rl, V);
-    const int64_t nrec = it.total / (V > 0 ? V : 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < it.total; i += stride) {
-        const int v = (int)(i / nrec);
-        const int64_t k = i - (int64_t)v * nrec;
-        list_one(a, rec_of(a.rl, it.na, k), v);
+        const int v = (int)(i / it.nrec);
+        const int64_t k = i - (int64_t)v * it.nrec;
+        list_one(a, rec_of(a.rl, it.na, k), v, (size_t)i);
     }
 }
 
@@ -491,7 +554,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const 
 // index order; within a round a key's rank among equal digits comes from ballots over
 // the digit's bits (in-wave) and the per-wave counts of lower waves (LDS).
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
-                                                       uint32_t *keys_out, uint32_t *vals_out, const uint32_t *nptr,
+                                                       const uint32_t *recs_in, uint32_t *keys_out,
+                                                       uint32_t *vals_out, uint32_t *recs_out, const uint32_t *nptr,
                                                        int shift, const uint32_t *hist_off)
 {
     __shared__ uint32_t run[256];
@@ -506,7 +570,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
     for (uint64_t base = lo; base < hi; base += 256) {
         const uint64_t i = base + tid;
         const bool valid = i < hi;
-        const uint32_t key = valid ? keys_in[i] : 0u, val = valid ? vals_in[i] : 0u;
+        const uint32_t key = valid ? keys_in[i] : 0u, val = valid ? vals_in[i] : 0u, rec = valid ? recs_in[i] : 0u;
         const uint32_t d = (key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -523,24 +587,12 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
             for (int w = 0; w < wave; ++w) pos += wc[w][d];
             keys_out[pos] = key;
             vals_out[pos] = val;
+            recs_out[pos] = rec;
         }
         __syncthreads();
         run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
         for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
         __syncthreads();
-    }
-}
-
-// sorted entry p: its record and its unsorted slot
-__global__ __launch_bounds__(256) void k_finalize(const uint32_t *vals, const uint32_t *rec_of, const uint32_t *nptr,
-                                                  uint32_t *entries, uint32_t *orig, uint64_t cap)
-{
-    const uint64_t n = *nptr;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n && p < cap; p += stride) {
-        const uint32_t o = vals[p];
-        orig[p] = o;
-        entries[p] = rec_of[o];
     }
 }
 
@@ -569,30 +621,31 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint32_t *keys, const
 
 void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
 {
-    const int64_t npairs = (int64_t)b.n_views * rl.Rcap;
-    if (npairs <= 0) return;
-    launch_scan_u32(b.nhits, b.hoff, npairs, b.scan_tmp, s);
-    ListArgs la{rl, b, npairs};
+    if ((int64_t)b.n_views * rl.Rcap <= 0) return;
+    ListArgs la{rl, b};
+    hipLaunchKernelGGL(k_pair_count, dim3(1), dim3(1), 0, s, la);
+    launch_scan_u32_dev(b.nhits, b.hoff, b.counters + CNT_NPAIRS, b.scan_tmp, s);
     hipLaunchKernelGGL(k_list_total, dim3(1), dim3(1), 0, s, la);
     hipLaunchKernelGGL(k_list, dim3(kRecBlocks), dim3(256), 0, s, la);
-    // keys are tile * 2 + class < 2 T: as many 8-bit digits as that needs
+    // keys are tile * 2 + class < 2 T: as many 8-bit digits as that needs (>= 1); the
+    // last pass writes the unsorted slots to `orig` and the records to `entries`
     const uint32_t kmax = 2u * (uint32_t)b.T;
     int bits = 0;
     while (bits < 32 && (kmax >> bits) != 0) ++bits;
-    const int passes = bits == 0 ? 0 : (bits + 7) / 8;
+    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
     const uint32_t *nptr = b.counters + CNT_SORT_N;
     int cur = 0;
     for (int ps = 0; ps < passes; ++ps) {
+        const bool last = ps == passes - 1;
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur], nptr, 8 * ps,
                            b.hist);
         launch_scan_u32(b.hist, b.hist_off, 256 * (int64_t)kSortGrid, b.scan_tmp, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur],
-                           (const uint32_t *)b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], nptr, 8 * ps,
+                           (const uint32_t *)b.vals[cur], (const uint32_t *)b.recs[cur], b.keys[cur ^ 1],
+                           last ? b.orig : b.vals[cur ^ 1], last ? b.entries : b.recs[cur ^ 1], nptr, 8 * ps,
                            (const uint32_t *)b.hist_off);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(kRecBlocks), dim3(256), 0, s, (const uint32_t *)b.vals[cur],
-                       (const uint32_t *)b.rec_of, nptr, b.entries, b.orig, (uint64_t)b.pair_cap);
     hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((b.T + 255) / 256)), dim3(256), 0, s,
                        (const uint32_t *)b.keys[cur], nptr, b);
     launch_scan_tiles(b, s);

@@ -61,7 +61,7 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
     size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, orig, keys0, keys1, vals0,
-        vals1, rec_of, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, total;
+        vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, total;
     uint32_t max_chunks;
     int T;
     int64_t total_px, Acap, Rcap;
@@ -171,7 +171,8 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.keys1 = o; o = align256(o + 4 * pc);
     p.vals0 = o; o = align256(o + 4 * pc);
     p.vals1 = o; o = align256(o + 4 * pc);
-    p.rec_of = o; o = align256(o + 4 * pc);
+    p.recs0 = o; o = align256(o + 4 * pc);
+    p.recs1 = o; o = align256(o + 4 * pc);
     p.hist = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
     p.hist_off = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
     p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
@@ -207,7 +208,8 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.keys[1] = (uint32_t *)(w + p.keys1);
     b.vals[0] = (uint32_t *)(w + p.vals0);
     b.vals[1] = (uint32_t *)(w + p.vals1);
-    b.rec_of = (uint32_t *)(w + p.rec_of);
+    b.recs[0] = (uint32_t *)(w + p.recs0);
+    b.recs[1] = (uint32_t *)(w + p.recs1);
     b.hist = (uint32_t *)(w + p.hist);
     b.hist_off = (uint32_t *)(w + p.hist_off);
     b.rec = (Rec *)(w + p.rec);
@@ -340,7 +342,6 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
-    fill_u32(b.nhits, (size_t)n_views * p.Rcap, 0u, s);
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
     launch_binning(rl, b, s);
     const KTimer bau_t{g_ev[0], g_ev[1]}, fwd_t{g_ev[2], g_ev[3]};

@@ -19,8 +19,9 @@ constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (e
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
 // CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue counters
-// CNT_SORT_N: tile entries that fit the pair capacity (the sorted list's length)
-enum { CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
+// CNT_NPAIRS: (listed record, view) pairs of the call; CNT_SORT_N: tile entries that fit
+// the pair capacity (the sorted list's length)
+enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
        CNT_SLOTS = 16 };
 constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
@@ -53,18 +54,19 @@ struct Buffers {
     uint32_t *cnt_a, *cnt_d;                    // [T] active / label-change entries per tile
     uint32_t *tile_off, *chunk_off;             // [T + 1]
     uint32_t *chunk_tile;                       // [max_chunks] tile of each backward work item
-    // Tile entries.  Every (record, view) pair owns the slots [hoff, hoff + nhits) of the
-    // unsorted list, one per tile it reaches; the list is sorted by (tile, class) into
-    // `entries` (record index) and `orig` (the entry's unsorted slot).
+    // Tile entries.  Every (listed record, view) pair -- index view * nrec + k for the
+    // k-th listed record, nrec = listed records of the call -- owns the slots
+    // [hoff, hoff + nhits) of the unsorted list, one per tile it reaches; the list is
+    // sorted by (tile, class) into `entries` (record index) and `orig` (the entry's
+    // unsorted slot).
     uint32_t *entries;                          // [pair_cap]
     uint32_t *orig;                             // [pair_cap]
-    uint32_t *keys[2], *vals[2];                // [pair_cap] radix-sort buffers
-    uint32_t *rec_of;                           // [pair_cap] record of each unsorted slot
+    uint32_t *keys[2], *vals[2], *recs[2];      // [pair_cap] radix-sort buffers
     uint32_t *hist, *hist_off;                  // [256][kSortGrid] digit counts and their scan
     Rec *rec;                                   // [V][Rcap]
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
-    uint32_t *nhits;                            // [V][Rcap] tiles the (record, view) pair reaches
-    uint32_t *hoff;                             // [V][Rcap] exclusive scan of nhits
+    uint32_t *nhits;                            // [pairs] tiles the (listed record, view) pair reaches
+    uint32_t *hoff;                             // [pairs] exclusive scan of nhits
     uint32_t *scan_tmp;                         // block sums of the device-wide scans
     float *ep;                                  // [pair_cap][kEpStride] screen-space partials, by unsorted slot
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
