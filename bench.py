@@ -136,7 +136,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     torch.cuda.synchronize()
     oit.clear_status(t.r.ws)
     log(f"{name}: timing {steps} {'eager steps' if eager else 'graph replays'}")
-    step_ms, pairs, evals, entries, chunks = [], [], [], [], []
+    step_ms, pairs, evals, entries, chunks, boxes = [], [], [], [], [], []
     for _ in range(steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -149,6 +149,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         pairs.append(c[1])
         evals.append(c[2])
         chunks.append(c[3])
+        boxes.append(c[4])
     # kernel timing pass: eager steps with kernel-bracketing events, and the pair
     # counters of the same launches
     ksteps = max(3, steps // 2)
@@ -180,6 +181,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         "evals": statistics.mean(evals),
         "entries": statistics.mean(entries),
         "chunks": statistics.mean(chunks),
+        "box_items": statistics.mean(boxes),
         "loss": loss,
         "active": t.k,
         "tile": t.r.tuning.tile,
@@ -352,7 +354,7 @@ def main():
         },
         "active": {"ms_per_step": round(act["ms_per_step"], 4), "ms_median": round(act["ms_per_step_median"], 4),
                    "evals_per_s": value, "contributing_pairs": act["pairs"], "evaluated_pairs": act["evals"],
-                   "tile_entries": act["entries"], "bwd_work_items": act["chunks"],
+                   "tile_entries": act["entries"], "bwd_work_items": act["chunks"], "bwd_box_items": act["box_items"],
                    "raster_fwd_ms": round(act["raster_fwd_ms"], 4), "raster_bwd_ms": round(act["raster_bwd_ms"], 4),
                    "loss": act["loss"], "autotune": act["tuned"]},
         "roofline": roofline,
@@ -363,6 +365,7 @@ def main():
                          "evals_per_s": dense["pairs"] / (dense["ms_per_step"] * 1e-3),
                          "contributing_pairs": dense["pairs"], "evaluated_pairs": dense["evals"],
                          "tile_entries": dense["entries"], "bwd_work_items": dense["chunks"],
+                         "bwd_box_items": dense["box_items"],
                          "raster_fwd_ms": round(dense["raster_fwd_ms"], 4),
                          "raster_bwd_ms": round(dense["raster_bwd_ms"], 4)}
         line["speedup_active_vs_dense"] = round(dense["ms_per_step"] / act["ms_per_step"], 3)

@@ -294,13 +294,15 @@ oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m,
 oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream);
 
 /*
- * Wait for `stream` and copy the counters the last oit_render_fwd on this workspace
- * left (arguments as given to that call; out (host) [4]):
- *   out[0] (tile, splat) entries it needed (also when it overflowed tuning.pair_capacity,
- *          so a caller can size pair_capacity and run again),
+ * Wait for `stream` and copy the counters the last oit_render_fwd / oit_render_bwd on
+ * this workspace left (arguments as given to that call; out (host) [5]):
+ *   out[0] (tile, splat) entries the forward needed (also when it overflowed
+ *          tuning.pair_capacity, so a caller can size pair_capacity and run again),
  *   out[1] contributing (alpha >= 1/255) active (splat, pixel) pairs it blended,
  *   out[2] active (splat, pixel) pairs it evaluated (tile entries x in-image tile pixels),
- *   out[3] backward work items (64 active entries of one tile each).
+ *   out[3] backward work items (up to 64 active entries of one tile each),
+ *   out[4] of those, the items the last backward walked footprint box by footprint box
+ *          (small footprints) instead of pixel group by pixel group.
  */
 oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity *cap,
                              const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,

@@ -238,6 +238,23 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, i
     }
 }
 
+// Box mode is taken when the largest footprint box is at most kBoxPerGroup pixels per
+// reached group: a box pixel costs about three times a group pixel slot (its own
+// exponent terms, a memory read of the constants, the full moments), and a group costs
+// 64 slots.
+constexpr int kBoxPerGroup = 21;
+
+// The entry's 10 screen-space partials from the lane's sums:
+// de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
+// de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy); the ln 2 of d alpha / de.
+__device__ __forceinline__ void write_partials(float *dst, float qa, float qb, float qc, const BwdSums &o)
+{
+    ((float4 *)dst)[0] = make_float4(-(2.f * qa * o.m_x + qb * o.m_y) * kLn2, -(qb * o.m_x + 2.f * qc * o.m_y) * kLn2,
+                                     o.m_xx * kLn2, o.m_xy * kLn2);
+    ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, o.g_cr, o.g_cg);
+    ((float2 *)dst)[4] = make_float2(o.g_cb, o.g_w);
+}
+
 template <int S>
 __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
                                          float4 (*s_c)[64], float (*s_B)[64])
@@ -301,9 +318,79 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         return;
     }
 
+    const size_t pb = (size_t)cam.pix_base;
+    const bool may_cap = __ballot(valid && lo > kLog2NoCap) != 0;
+
+    // Small footprints (typical of sub-pixel splats): each lane walks its own box,
+    // reading the pixel constants it needs from memory, instead of the whole wave
+    // walking every reached group.  The box holds every pixel whose exponent can pass
+    // the threshold (same widened extents).
+    {
+        int bc0 = 0, bc1 = -1, br0 = 0, br1 = -1;   // tile-local columns / rows of the box
+        if (hx >= 0.f) {
+            const float lim = 1e6f;
+            bc0 = max(0, (int)ceilf(fmaxf(-hx - dx0, -lim)));
+            bc1 = min(min(S, cam.W - tx * S) - 1, (int)floorf(fminf(hx - dx0, lim)));
+            br0 = max(0, (int)ceilf(fmaxf(-hy - dy0, -lim)));
+            br1 = min(min(S, cam.H - ty * S) - 1, (int)floorf(fminf(hy - dy0, lim)));
+        }
+        const int area = (bc1 >= bc0 && br1 >= br0) ? (bc1 - bc0 + 1) * (br1 - br0 + 1) : 0;
+        int amax = area;
+        for (int m = 32; m > 0; m >>= 1) amax = max(amax, __shfl_xor(amax, m));
+        if (amax <= kBoxPerGroup * __builtin_popcount(mask)) {
+            if (lane == 0) atomicAdd(&b.counters[CNT_BOX_ITEMS], 1u);
+            BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            int c = bc0, r = br0;
+            // the constants of the lane's next box pixel are fetched one pixel ahead
+            const size_t row0 = pb + (size_t)(ty * S) * cam.W + (size_t)(tx * S);
+            float4 npc = make_float4(0.f, 0.f, 0.f, 0.f);
+            float nBc = 0.f;
+            if (area > 0) {
+                npc = b.pixconst[row0 + (size_t)r * cam.W + c];
+                nBc = b.pixB[row0 + (size_t)r * cam.W + c];
+            }
+            for (int k = 0; k < amax; ++k) {
+                if (k < area) {
+                    const float4 pc = npc;
+                    const float Bc = nBc;
+                    const float dx = dx0 + (float)c, dy = dy0 + (float)r;
+                    if (++c > bc1) {
+                        c = bc0;
+                        ++r;
+                    }
+                    if (k + 1 < area) {
+                        npc = b.pixconst[row0 + (size_t)r * cam.W + c];
+                        nBc = b.pixB[row0 + (size_t)r * cam.W + c];
+                    }
+                    const float e = exp_pix(qc, dy, exp_col_b(qb, dx), exp_col_c(qa, lo, dx));
+                    if (e >= kLog2AlphaMin) {
+                        const float ex = __builtin_amdgcn_exp2f(e);
+                        const float al = may_cap ? fminf(ex, kAlphaMax) : ex;
+                        const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
+                        const float aw = al * w;
+                        o.g_cr = fmaf(pc.x, aw, o.g_cr);
+                        o.g_cg = fmaf(pc.y, aw, o.g_cg);
+                        o.g_cb = fmaf(pc.z, aw, o.g_cb);
+                        o.g_w = fmaf(al, diff, o.g_w);
+                        const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                        const float dLde = (al < kAlphaMax ? al : 0.f) * dLda;
+                        const float exx = dLde * dx, eyy = dLde * dy;
+                        o.m0 += dLde;
+                        o.m_x += exx;
+                        o.m_y += eyy;
+                        o.m_xx = fmaf(exx, dx, o.m_xx);
+                        o.m_xy = fmaf(exx, dy, o.m_xy);
+                        o.m_yy = fmaf(eyy, dy, o.m_yy);
+                    }
+                }
+            }
+            if (valid) write_partials(dst, qa, qb, qc, o);
+            return;
+        }
+    }
+
     // this lane's pixel when staging a group's constants
     const int sx = lane % kGroup, sy = lane / kGroup;
-    const size_t pb = (size_t)cam.pix_base;
     auto fetch = [&](int g, float4 &c, float &Bv) {
         const int x = tx * S + (g % GX) * kGroup + sx, y = ty * S + (g / GX) * kGroup + sy;
         c = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -316,7 +403,6 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     };
 
     BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const bool may_cap = __ballot(valid && lo > kLog2NoCap) != 0;
     int g = __builtin_ctz(mask);
     mask &= mask - 1;
     float4 nc;
@@ -341,14 +427,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         if (gn < 0) break;
         g = gn;
     }
-    if (valid) {
-        // de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
-        // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy)
-        ((float4 *)dst)[0] = make_float4(-(2.f * qa * o.m_x + qb * o.m_y) * kLn2,
-                                         -(qb * o.m_x + 2.f * qc * o.m_y) * kLn2, o.m_xx * kLn2, o.m_xy * kLn2);
-        ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, o.g_cr, o.g_cg);
-        ((float2 *)dst)[4] = make_float2(o.g_cb, o.g_w);
-    }
+    if (valid) write_partials(dst, qa, qb, qc, o);
 }
 
 template <int S>

@@ -467,6 +467,7 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
                      grads->stride};
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
+    fill_u32(b.counters + CNT_BOX_ITEMS, 1, 0u, s);
     fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
     const KTimer bwd_t{g_ev[4], g_ev[5]};
@@ -620,6 +621,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
     out[1] = (int64_t)((uint64_t)v[CNT_PAIRS] | ((uint64_t)v[CNT_PAIRS + 1] << 32));
     out[2] = (int64_t)((uint64_t)v[CNT_EVAL] | ((uint64_t)v[CNT_EVAL + 1] << 32));
     out[3] = (int64_t)v[CNT_TOTAL_CHUNKS];
+    out[4] = (int64_t)v[CNT_BOX_ITEMS];
     return ok();
 }
 

@@ -21,8 +21,9 @@ constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (e
 // CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue counters
 // CNT_NPAIRS: (listed record, view) pairs of the call; CNT_SORT_N: tile entries that fit
 // the pair capacity (the sorted list's length)
+// CNT_BOX_ITEMS: backward work items that took the footprint-box walk
 enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
-       CNT_SLOTS = 16 };
+       CNT_BOX_ITEMS = 16, CNT_SLOTS = 32 };
 constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
 struct SplatPtrs {

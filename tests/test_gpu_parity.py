@@ -83,6 +83,40 @@ def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True,
     return r
 
 
+def backward_walk_counts(sc, tile=16):
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n, tile=tile, batch=64)
+    r.fit_pair_capacity(params, sigma, sc.background)
+    r.forward(params, sigma, sc.background)
+    gimg = torch.ones(3 * r.total_px, device=DEV)
+    r.backward(params, sigma, sc.background, gimg, new_grads(sc.n, DEV),
+               torch.zeros(1, dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    c = r.counters()
+    return c[3], c[4]
+
+
+def test_backward_walks_both_ways():
+    """The backward walks small footprints box by box and large ones group by group; the
+    config-1 parity cases at tile 16 contain work items of both kinds, the sub-pixel
+    case below almost only box walks."""
+    items, boxed = backward_walk_counts(scenes.make_scene(1))
+    log(f"  config 1: {items} backward work items, {boxed} walked box by box")
+    assert 0 < boxed < items
+    items, boxed = backward_walk_counts(scenes.make_scene(1, log_scale_mu=-6.0))
+    log(f"  config 1, sub-pixel splats: {items} backward work items, {boxed} walked box by box")
+    assert boxed > items // 2
+
+
+def test_subpixel_scene_parity():
+    """Sub-pixel splats (log-scale ~ N(-6, 0.3)): images and gradients against the
+    oracle, with the backward walking footprint boxes."""
+    for tile in (8, 16, 32):
+        log(f"sub-pixel scene, tile {tile}")
+        dense_case(scenes.make_scene(1, log_scale_mu=-6.0), tile=tile, batch=64)
+
+
 @pytest.mark.parametrize("tile,batch", [(16, 64), (8, 32), (32, 256), (16, 128)])
 def test_tiny_dense_parity(tile, batch):
     log(f"tiny dense parity tile={tile} batch={batch}")
