@@ -226,6 +226,49 @@ def ablation(scene, steps, tile, batch):
     return out
 
 
+def schedule_bench(scene, iters, interval, fraction, tile, batch):
+    """The paper's schedule (Sec. 4.1): one training view per iteration, the active set
+    recomputed every `interval` iterations on FPS-subsampled views with an epsilon
+    threshold (chosen here from the scores so that about `fraction` of the splats are
+    active), L1 + D-SSIM; and the same loop with every splat active beside it."""
+    import numpy as np
+    import torch
+    from paper_2605_13855_amd.schedule import PaperScheduleTrainer
+
+    nv = len(scene.cameras)
+    probe = PaperScheduleTrainer(scene, eps=[1.0] * 6, interval=interval, n_sub=nv, tile=tile, batch=batch)
+    probe.update_active_set()
+    eps = [float(np.quantile(probe.score.cpu().numpy(), 1.0 - fraction))] * 6
+    del probe
+    torch.cuda.empty_cache()
+    out = {}
+    for name, e in (("active", eps), ("all_active", [1e-30] * 6)):
+        t = PaperScheduleTrainer(scene, eps=e, interval=interval, n_sub=nv, tile=tile, batch=batch)
+        for _ in range(nv):          # one pass over the views grows the capacities
+            t.iteration()
+        torch.cuda.synchronize()
+        ms, fracs = [], [round(t.active_fraction(), 4)]
+        for _ in range(iters):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            upd = t.it % interval == 0
+            e0.record()
+            t.iteration()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            if upd:
+                fracs.append(round(t.active_fraction(), 4))
+        upd = [m for i, m in enumerate(ms) if (nv + i) % interval == 0]
+        out[name] = {"ms_per_iter": round(statistics.mean(ms), 4), "ms_median": round(statistics.median(ms), 4),
+                     "update_iters_ms": [round(x, 3) for x in upd], "active_fraction_per_update": fracs,
+                     "rebuilds": t.rebuilds}
+        log(f"schedule {name}: {out[name]}")
+        del t
+        torch.cuda.empty_cache()
+    out["speedup"] = round(out["all_active"]["ms_per_iter"] / out["active"]["ms_per_iter"], 3)
+    return out
+
+
 def cpu_baseline(scene, budget_s=20.0):
     """The FP64 oracle, single-threaded, on a window of view 0 (all splats), fwd + bwd."""
     import numpy as np
@@ -273,6 +316,10 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark line, time the per-splat against the per-pixel backward "
                          "(dense; default config 2)")
+    ap.add_argument("--schedule", action="store_true",
+                    help="instead of the benchmark line, time the paper's active-set schedule (one view per "
+                         "iteration, FPS-subsampled threshold updates, L1 + D-SSIM) against all splats active")
+    ap.add_argument("--interval", type=int, default=50, help="active-set update interval for --schedule")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -302,6 +349,15 @@ def main():
         res = ablation(scene, args.steps, args.tile, args.batch)
         print(json.dumps({"ablation": res, "config": {"workload": f"config {cfg}: {scene.n} splats, "
                           f"{len(scene.cameras)} view(s), dense fwd+bwd, L1"}}), flush=True)
+        return
+    if args.schedule:
+        scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
+        res = schedule_bench(scene, args.steps, args.interval, args.fraction, args.tile, args.batch)
+        print(json.dumps({"schedule": res, "config": {
+            "workload": f"config {args.config}: {scene.n} splats, {len(scene.cameras)} views, one view per "
+                        f"iteration, update every {args.interval} iterations on all views (FPS), "
+                        f"~{args.fraction:.0%} active, L1 + D-SSIM", "tile": args.tile, "batch": args.batch}}),
+              flush=True)
         return
     log(f"building scene config {args.config}")
     scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)

@@ -19,9 +19,13 @@
  *
  * Conventions for every entry point
  *   - Pointers are DEVICE pointers unless marked (host).
- *   - Splat parameters are float32, component-major ("SoA"): a group with C components
- *     is a [C][n] array (row c at offset c * n).  The colour SH is [16][3][n]
- *     (coefficient, channel, splat); quaternions are (w, x, y, z), any length.
+ *   - Splat parameters (and Adam's moments) are float32, splat-major: a group with C
+ *     components is an [n][C] array (splat i's components at offset i * C), so the rows
+ *     of a sparse active set are read and written in whole segments.  The colour SH is
+ *     [n][16][3] (splat, coefficient, channel); quaternions are (w, x, y, z), any
+ *     length.  quat, sh and vsh start on 16-byte boundaries (vector loads).
+ *   - Gradients of active rows are compact and component-major: a group with C
+ *     components is a [C][stride] array whose column r is active row r.
  *   - Per-view images are planar float32.  A batch of V views is packed view after
  *     view: view k starts at plane offset P * pix_base(k), pix_base(k) = sum_{j<k} H_j W_j,
  *     and holds P planes of H_k x W_k (P = 3 for images, 5 for pixstate, 9 for pre).
@@ -76,12 +80,12 @@ typedef struct {
 
 typedef struct {
     int64_t n;
-    const float *mean;          /* [3][n] */
-    const float *log_scale;     /* [3][n]   scale = exp(log_scale) */
-    const float *quat;          /* [4][n]   (w, x, y, z) */
+    const float *mean;          /* [n][3] */
+    const float *log_scale;     /* [n][3]   scale = exp(log_scale) */
+    const float *quat;          /* [n][4]   (w, x, y, z); 16-byte aligned */
     const float *opacity_logit; /* [n]      opacity = sigmoid(logit) */
-    const float *sh;            /* [16][3][n] colour SH, degree 3 */
-    const float *vsh;           /* [16][n]  view-weight SH, degree 3 */
+    const float *sh;            /* [n][16][3] colour SH, degree 3; 16-byte aligned */
+    const float *vsh;           /* [n][16]  view-weight SH, degree 3; 16-byte aligned */
 } oit_splats;
 
 /* Gradients of the active rows, compact: row r of a group is the r-th entry of
@@ -271,7 +275,7 @@ oit_status oit_fps_views(const float *centres, int32_t n, int32_t s, int32_t sta
  * component:  m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
  *             theta -= lr_g * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
  * Rows outside the active set, their moments included, are not touched.
- * params/m/v  [6] pointers to the [C][n] groups (mean, log_scale, quat, opacity_logit,
+ * params/m/v  [6] pointers to the [n][C] groups (mean, log_scale, quat, opacity_logit,
  *             sh, vsh); grads as written by oit_render_bwd
  * active_idx  NULL for dense (all n rows); n_active device count or NULL (= n)
  * lr          (host) [6] per-group learning rates

@@ -13,41 +13,72 @@ struct AdamArgs {
     const int32_t *idx;
     const int32_t *n_active;
     int64_t n;
+    int64_t rows_cap;   // compact gradient rows available (the device count is clamped to it)
     float b1, b2, eps;
     const int32_t *step;
 };
 
-__device__ __constant__ const int kGroupStart[7] = {0, 3, 6, 10, 11, 59, 75};
+// One block per tile of kRows active rows of one attribute group (grid.y = group),
+// grid-stride over the tiles with a fixed grid (the row count is read on the device).
+// The tile's gradients arrive component-major ([C][stride], one coalesced run per
+// component) and are transposed through LDS, so that the parameters and both moments
+// ([n][C]) are read and written in whole per-splat segments.
+constexpr int kAdamThreads = 256;
+constexpr int kRows = 64;
+constexpr unsigned kAdamTiles = 1024;
 
-// grid.y = component (75), grid.x covers the active rows
-__global__ __launch_bounds__(256) void k_sparse_adam(AdamArgs a)
+template <int C>
+__device__ void adam_group(const AdamArgs &a, int grp, int64_t na, float bc1, float bc2, float *s_g,
+                           int64_t *s_id)
 {
-    // bias corrections of this step, once per block
-    __shared__ float s_bc[2];
+    float *p = a.p.p[grp], *m = a.p.m[grp], *v = a.p.v[grp];
+    const float *g = a.p.g[grp];
+    const float lr = a.p.lr[grp];
+    const int64_t ntiles = (na + kRows - 1) / kRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kRows;
+        const int rows = (int)min((int64_t)kRows, na - r0);
+        for (int e = threadIdx.x; e < C * kRows; e += kAdamThreads) {
+            const int c = e / kRows, j = e % kRows;
+            if (j < rows) s_g[c * (kRows + 1) + j] = g[(size_t)c * a.gstride + r0 + j];
+        }
+        if (threadIdx.x < rows) s_id[threadIdx.x] = a.idx ? (int64_t)a.idx[r0 + threadIdx.x] : r0 + threadIdx.x;
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * C; e += kAdamThreads) {
+            const int j = e / C, c = e % C;
+            const size_t pi = (size_t)s_id[j] * C + c;
+            const float gg = s_g[c * (kRows + 1) + j];
+            const float mm = a.b1 * m[pi] + (1.f - a.b1) * gg;
+            const float vv = a.b2 * v[pi] + (1.f - a.b2) * gg * gg;
+            m[pi] = mm;
+            v[pi] = vv;
+            p[pi] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + a.eps);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kAdamThreads) void k_sparse_adam(AdamArgs a)
+{
+    __shared__ float s_g[48 * (kRows + 1)];   // the largest group (colour SH), padded rows
+    __shared__ int64_t s_id[kRows];
+    __shared__ float s_bc[2];                 // bias corrections of this step
     if (threadIdx.x == 0) {
         const float t = (float)*a.step;
         s_bc[0] = 1.f - powf(a.b1, t);
         s_bc[1] = 1.f - powf(a.b2, t);
     }
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t na = a.n_active ? (int64_t)*a.n_active : a.n;
-    if (r >= na) return;
-    const int c = blockIdx.y;
-    int grp = 0;
-#pragma unroll
-    for (int k = 1; k < 6; ++k)
-        if (c >= kGroupStart[k]) grp = k;
-    const int sub = c - kGroupStart[grp];
-    const int64_t id = a.idx ? (int64_t)a.idx[r] : r;
-    const size_t pi = (size_t)sub * a.n + id;
-    const float g = a.p.g[grp][(size_t)sub * a.gstride + r];
+    const int64_t na = a.n_active ? min((int64_t)*a.n_active, a.rows_cap) : a.n;
     const float bc1 = s_bc[0], bc2 = s_bc[1];
-    const float m = a.b1 * a.p.m[grp][pi] + (1.f - a.b1) * g;
-    const float v = a.b2 * a.p.v[grp][pi] + (1.f - a.b2) * g * g;
-    a.p.m[grp][pi] = m;
-    a.p.v[grp][pi] = v;
-    a.p.p[grp][pi] -= a.p.lr[grp] * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+    switch (blockIdx.y) {
+    case 0: adam_group<3>(a, 0, na, bc1, bc2, s_g, s_id); break;
+    case 1: adam_group<3>(a, 1, na, bc1, bc2, s_g, s_id); break;
+    case 2: adam_group<4>(a, 2, na, bc1, bc2, s_g, s_id); break;
+    case 3: adam_group<1>(a, 3, na, bc1, bc2, s_g, s_id); break;
+    case 4: adam_group<48>(a, 4, na, bc1, bc2, s_g, s_id); break;
+    default: adam_group<16>(a, 5, na, bc1, bc2, s_g, s_id); break;
+    }
 }
 
 void launch_sparse_adam(const AdamPtrs &p, int64_t gstride, const int32_t *active_idx, const int32_t *n_active,
@@ -55,9 +86,10 @@ void launch_sparse_adam(const AdamPtrs &p, int64_t gstride, const int32_t *activ
                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, step);
-    AdamArgs a{p, gstride, active_idx, n_active, n, b1, b2, eps, step};
-    const unsigned bx = (unsigned)((rows_cap + 255) / 256);
-    if (bx) hipLaunchKernelGGL(k_sparse_adam, dim3(bx, 75), dim3(256), 0, s, a);
+    AdamArgs a{p, gstride, active_idx, n_active, n, rows_cap, b1, b2, eps, step};
+    const int64_t tiles = (rows_cap + kRows - 1) / kRows;
+    const unsigned bx = (unsigned)min((int64_t)kAdamTiles, tiles);
+    if (bx) hipLaunchKernelGGL(k_sparse_adam, dim3(bx, 6), dim3(kAdamThreads), 0, s, a);
 }
 
 __global__ void k_sigma_adam(float *sigma, const double *g, float *m, float *v, float lr, float b1, float b2,

@@ -629,7 +629,8 @@ struct ViewPart {
 __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int64_t id, int v, const float mu[3],
                               const float S6[6], float sigma, ViewPart &o)
 {
-    const int64_t n = a.sp.n;
+    const float *sh = a.sp.sh + 48 * id;    // [16][3] of this splat
+    const float *vsh = a.sp.vsh + 16 * id;
 #pragma unroll
     for (int k = 0; k < 3; ++k) o.g_mu[k] = 0.f;
 #pragma unroll
@@ -691,18 +692,18 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
     for (int ch = 0; ch < 3; ++ch) {
         float raw = kColorOffset;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) raw += o.Y[k] * a.sp.sh[(3 * k + ch) * n + id];
+        for (int k = 0; k < 16; ++k) raw += o.Y[k] * sh[3 * k + ch];
         if (raw > 0.f) {
             const float gc = gs[6 + ch];
             o.gcm[ch] = gc;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) gY[k] = fmaf(gc, a.sp.sh[(3 * k + ch) * n + id], gY[k]);
+            for (int k = 0; k < 16; ++k) gY[k] = fmaf(gc, sh[3 * k + ch], gY[k]);
         }
     }
     {
         float raw = kColorOffset;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) raw += o.Y[k] * a.sp.vsh[k * n + id];
+        for (int k = 0; k < 16; ++k) raw += o.Y[k] * vsh[k];
         const float vv = fmaxf(raw, 0.f);
         const float gw = gs[9];
         if (tz < sigma) {
@@ -712,7 +713,7 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
             if (raw > 0.f) {
                 o.gvm = gv;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) gY[k] = fmaf(gv, a.sp.vsh[k * n + id], gY[k]);
+                for (int k = 0; k < 16; ++k) gY[k] = fmaf(gv, vsh[k], gY[k]);
             }
         }
     }
@@ -802,7 +803,6 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
     const int P = a.vlanes, V = a.b.n_views;
     const int rows_per_block = kPbThreads / P;
     const int lr = threadIdx.x / P, vl = threadIdx.x % P;
-    const int64_t n = a.sp.n;
     const int64_t st = a.g.stride;
     int64_t na = a.rl.n_active ? (int64_t)*a.rl.n_active : a.rl.n_active_host;
     na = na < 0 ? 0 : (na > a.rl.Acap ? a.rl.Acap : na);
@@ -821,12 +821,12 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
         if (row_ok) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                mu[k] = a.sp.mean[k * n + id];
-                s3[k] = expf(a.sp.log_scale[k * n + id]);
+                mu[k] = a.sp.mean[3 * id + k];
+                s3[k] = expf(a.sp.log_scale[3 * id + k]);
             }
             float q[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[k * n + id];
+            for (int k = 0; k < 4; ++k) q[k] = a.sp.quat[4 * id + k];
             qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) qn[k] = q[k] * qi;

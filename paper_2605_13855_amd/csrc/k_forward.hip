@@ -131,18 +131,22 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
     const int64_t id = record_row(a.rl, t, sign);
     if (id < 0) return;
     const SplatPtrs &sp = sign == 0 ? a.sp : a.dsp;
-    const int64_t n = sp.n;
     const CamDev &cam = a.b.cams[v];
     const size_t ri = (size_t)v * a.rl.Rcap + t;
 
     float mu[3], s3[3], q[4];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        mu[k] = sp.mean[k * n + id];
-        s3[k] = expf(sp.log_scale[k * n + id]);
+        mu[k] = sp.mean[3 * id + k];
+        s3[k] = expf(sp.log_scale[3 * id + k]);
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = sp.quat[k * n + id];
+    {
+        const float4 q4 = ((const float4 *)sp.quat)[id];
+        q[0] = q4.x;
+        q[1] = q4.y;
+        q[2] = q4.z;
+        q[3] = q4.w;
+    }
     const float qi = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     float Rq[9], S6[6];
     quat_rot(q[0] * qi, q[1] * qi, q[2] * qi, q[3] * qi, Rq);
@@ -163,11 +167,23 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
         sh_eval(dir[0], dir[1], dir[2], Y);
         float col[3] = {kColorOffset, kColorOffset, kColorOffset};
         float vr = kColorOffset;
+        // the splat's 48 colour and 16 view-weight coefficients: 16 contiguous float4
+        const float4 *sh4 = (const float4 *)sp.sh + 12 * id;
+        const float4 *vsh4 = (const float4 *)sp.vsh + 4 * id;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int j = 0; j < 12; ++j) {   // float4 j holds coefficients 4j .. 4j+3 of [16][3]
+            const float4 c4 = sh4[j];
+            const float cv[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * sp.sh[(3 * k + ch) * n + id];
-            vr += Y[k] * sp.vsh[k * n + id];
+            for (int e = 0; e < 4; ++e) col[(4 * j + e) % 3] += Y[(4 * j + e) / 3] * cv[e];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float4 c4 = vsh4[j];
+            vr += Y[4 * j] * c4.x;
+            vr += Y[4 * j + 1] * c4.y;
+            vr += Y[4 * j + 2] * c4.z;
+            vr += Y[4 * j + 3] * c4.w;
         }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.f);

@@ -240,7 +240,9 @@ oit_status check_splats(const oit_splats *s, const oit_capacity *cap)
     const char *names[6] = {"mean", "log_scale", "quat", "opacity_logit", "sh", "vsh"};
     for (int k = 0; k < 6; ++k) {
         if (!ptrs[k]) return fail(OIT_ERR_INVALID, "splats.%s is NULL", names[k]);
-        if (!aligned(ptrs[k], 4)) return fail(OIT_ERR_INVALID, "splats.%s is not 4-byte aligned", names[k]);
+        const size_t al = (k == 2 || k >= 4) ? 16 : 4;   // quat, sh and vsh rows are read as float4
+        if (!aligned(ptrs[k], al))
+            return fail(OIT_ERR_INVALID, "splats.%s is not %zu-byte aligned", names[k], al);
     }
     return OIT_OK;
 }

@@ -139,11 +139,11 @@ def camera_array(cams):
 
 
 def splats_struct(params: dict) -> Splats:
-    n = params["mean"].shape[1]
+    n = params["mean"].shape[0]
     for g, c in GROUPS:
         t = params[g]
-        if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (c, n):
-            raise OITError(f"parameter {g} must be contiguous float32 [{c}][{n}]")
+        if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (n, c):
+            raise OITError(f"parameter {g} must be contiguous float32 [{n}][{c}] (splat-major)")
     return Splats(n, *[params[g].data_ptr() for g, _ in GROUPS])
 
 
@@ -229,6 +229,11 @@ def fps_views(centres, s: int, start: int):
 def sparse_adam_step(params: dict, grads: Grads, m: dict, v: dict, active_idx, n_active, n, lr, beta1, beta2,
                      eps, step, stream=None):
     P6 = ctypes.c_void_p * 6
+    for g, c in GROUPS:
+        for name, d in (("params", params), ("m", m), ("v", v)):
+            t = d[g]
+            if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (int(n), c):
+                raise OITError(f"{name}[{g}] must be contiguous float32 [{int(n)}][{c}] (splat-major)")
     pp = P6(*[params[g].data_ptr() for g, _ in GROUPS])
     mm = P6(*[m[g].data_ptr() for g, _ in GROUPS])
     vv = P6(*[v[g].data_ptr() for g, _ in GROUPS])

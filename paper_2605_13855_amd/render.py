@@ -26,7 +26,14 @@ GROUPS = oit.GROUPS
 
 
 def params_to_device(params: dict, device="cuda") -> dict:
-    return {g: torch.as_tensor(params[g], dtype=torch.float32).to(device).contiguous() for g, _ in GROUPS}
+    """Component-major host arrays ([C][n], the scene generator's layout) to the
+    splat-major device tensors the library takes ([n][C])."""
+    return {g: torch.as_tensor(params[g], dtype=torch.float32).t().contiguous().to(device) for g, _ in GROUPS}
+
+
+def params_to_host(params: dict) -> dict:
+    """Splat-major device tensors back to component-major float32 host arrays."""
+    return {g: params[g].detach().t().contiguous().cpu().numpy() for g, _ in GROUPS}
 
 
 def _aligned_workspace(nbytes: int, device) -> torch.Tensor:
@@ -143,6 +150,22 @@ class Renderer:
     def pairs_needed(self) -> int:
         return self.counters()[0]
 
+    def forward_fitted(self, params, sigma, bg, active=None, pre=None, delta_params=None, slack=1.25):
+        """Forward that sizes the pair capacity as it goes: one run, then (after a status
+        read, which synchronises) a second one only when the tile lists overflowed.  The
+        label changes are folded into the pre-rendered buffer by the run, so a copy taken
+        before the first run is put back before the second."""
+        folds = pre is not None and active is not None and active.get("n_delta") is not None
+        backup = pre.clone() if folds else None
+        self.forward(params, sigma, bg, active, pre, delta_params)
+        if not self.status() & oit.STATUS_PAIR_OVERFLOW:
+            return self.image
+        need = self.pairs_needed()
+        self.set_tuning(pair_capacity=min(int(need * slack) + 4096, 2 ** 32 - 2))
+        if folds:
+            pre.copy_(backup)
+        return self.forward(params, sigma, bg, active, pre, delta_params)
+
     def fit_pair_capacity(self, params, sigma, bg, active=None, pre=None, slack=1.25, delta_params=None):
         """Run the forward once; grow the pair capacity if the tile lists overflowed."""
         pre_copy = pre.clone() if pre is not None else None
@@ -183,8 +206,9 @@ class OITRender(torch.autograd.Function):
     """Dense differentiable render of a batch of views.
 
     forward(renderer, sigma, mean, log_scale, quat, opacity_logit, sh, vsh) -> image
-    (packed [V][3][H][W]); backward returns the gradient of every parameter and of
-    sigma.  The per-pixel totals live in the renderer between the two passes.
+    (packed [V][3][H][W]); the parameters are splat-major ([n][3], [n][3], [n][4],
+    [n][1], [n][48], [n][16]).  backward returns the gradient of every parameter (same
+    shapes) and of sigma.  The per-pixel totals live in the renderer between the passes.
     """
 
     @staticmethod
@@ -205,8 +229,9 @@ class OITRender(torch.autograd.Function):
         grads = new_grads(r.n, sigma.device)
         gsig = torch.zeros(1, dtype=torch.float64, device=sigma.device)
         r.backward(ctx.params, sigma, ctx.bg, grad_image.contiguous(), grads, gsig)
-        return (None, gsig.to(sigma.dtype), grads["mean"], grads["log_scale"], grads["quat"],
-                grads["opacity_logit"], grads["sh"], grads["vsh"], None)
+        g = {k: t.t().contiguous() for k, t in grads.items()}   # compact [C][n] -> [n][C]
+        return (None, gsig.to(sigma.dtype), g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], g["sh"],
+                g["vsh"], None)
 
 
 def render(renderer, sigma, params, bg=(0.0, 0.0, 0.0)):
@@ -224,7 +249,7 @@ class ActiveSetTrainer:
         self.loss_fn = PhotometricLoss(loss, device=device)
         dev = self.device
         self.params = params_to_device(scene.params, dev)
-        self.n = self.params["mean"].shape[1]
+        self.n = self.params["mean"].shape[0]
         self.dense = dense
         self.k = self.n if dense else max(1, int(math.ceil(fraction * self.n)))
         self.bg = tuple(float(x) for x in scene.background)

@@ -37,7 +37,7 @@ class PaperScheduleTrainer:
         self.loss_fn = PhotometricLoss(loss, device=device)
         dev = self.device
         self.params = params_to_device(scene.params, dev)
-        self.n = self.params["mean"].shape[1]
+        self.n = self.params["mean"].shape[0]
         self.bg = tuple(float(x) for x in scene.background)
         self.cams = list(scene.cameras)
         self.targets = [torch.as_tensor(t, dtype=torch.float32).reshape(-1).to(dev) for t in scene.targets]
@@ -85,10 +85,6 @@ class PaperScheduleTrainer:
         self.last_update_views = []
         self.rebuilds = 0
 
-    # ----------------------------------------------------------------------------
-    def _fit(self, r, active=None, pre=None):
-        r.fit_pair_capacity(self.params, self.sigma, self.bg, active, pre)
-
     def update_active_set(self):
         """Activeness on FPS-subsampled views, then threshold selection (new epoch)."""
         start = int(self.rng.integers(len(self.cams)))
@@ -99,9 +95,8 @@ class PaperScheduleTrainer:
             self.sub = Renderer(cams, self.n, self.n, 0, self.r.tuning.tile, self.r.tuning.batch, None, self.device)
         else:
             self.sub.use_cameras(cams)
-        self._fit(self.sub)
         r = self.sub
-        r.forward(self.params, self.sigma, self.bg)
+        r.forward_fitted(self.params, self.sigma, self.bg)
         target = torch.cat([self.targets[i] for i in views])
         gi = torch.zeros_like(target)
         self.loss_fn(r, r.image, target, gi, self.loss)
@@ -150,18 +145,20 @@ class PaperScheduleTrainer:
         act = self.prepare_view(v)
         self.r.use_cameras([self.cams[v]])
         if fit:
-            self.r.fit_pair_capacity(self.params, self.sigma, self.bg, act, self.pre[v],
-                                     delta_params=self.snapshot)
-        self.r.forward(self.params, self.sigma, self.bg, act, self.pre[v], self.snapshot)
+            self.r.forward_fitted(self.params, self.sigma, self.bg, act, self.pre[v], self.snapshot)
+        else:
+            self.r.forward(self.params, self.sigma, self.bg, act, self.pre[v], self.snapshot)
         self.view_epoch[v] = self.epoch
         self._forget_labels()
         return act
 
-    def iteration(self):
+    def iteration(self, fit=True):
+        """One training iteration on the next view.  fit=False skips the status read that
+        grows the pair capacity on overflow (the caller then checks the status word)."""
         if self.it % self.interval == 0:
             self.update_active_set()
         v = self.next_view()
-        act = self.render_view(v)
+        act = self.render_view(v, fit)
         gi = self.grad_image[:3 * self.cams[v].width * self.cams[v].height]
         self.loss_fn(self.r, self.r.image, self.targets[v], gi, self.loss)
         self.r.backward(self.params, self.sigma, self.bg, gi, self.grads, self.grad_sigma, act, self.pre[v])

@@ -259,10 +259,11 @@ def test_sparse_adam_matches_oracle():
     rng = np.random.default_rng(9)
     n = 5000
     rows = np.sort(rng.choice(n, size=700, replace=False))
-    params = {g: torch.tensor(rng.normal(size=(c, n)), dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
-    m = {g: torch.tensor(rng.normal(size=(c, n)) * 0.01, dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
-    v = {g: torch.tensor(rng.random(size=(c, n)) * 0.01, dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
-    ref = {g: (to_np(params[g]).copy(), to_np(m[g]).copy(), to_np(v[g]).copy()) for g, _ in O.GROUPS}
+    host = {"p": {g: rng.normal(size=(c, n)) for g, c in O.GROUPS},
+            "m": {g: rng.normal(size=(c, n)) * 0.01 for g, c in O.GROUPS},
+            "v": {g: rng.random(size=(c, n)) * 0.01 for g, c in O.GROUPS}}
+    params, m, v = (params_to_device(host[k]) for k in ("p", "m", "v"))
+    ref = {g: tuple(host[k][g].astype(np.float32).astype(np.float64) for k in ("p", "m", "v")) for g, _ in O.GROUPS}
     acap = 1024
     grads = {g: torch.zeros((c, acap), device=DEV) for g, c in O.GROUPS}
     gv = {g: rng.normal(size=(c, len(rows))).astype(np.float32) for g, c in O.GROUPS}
@@ -280,18 +281,18 @@ def test_sparse_adam_matches_oracle():
     for k, (g, _) in enumerate(O.GROUPS):
         p0, m0, v0 = ref[g]
         O.adam_rows(p0, gv[g].astype(np.float64), m0, v0, rows, f32(lr[k]), f32(0.9), f32(0.999), f32(1e-15), 5)
-        np.testing.assert_allclose(to_np(params[g]), p0, rtol=1e-5, atol=1e-6)
-        np.testing.assert_allclose(to_np(m[g]), m0, rtol=1e-5, atol=1e-7)
-        np.testing.assert_allclose(to_np(v[g]), v0, rtol=1e-5, atol=1e-9)
+        np.testing.assert_allclose(to_np(params[g]).T, p0, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(to_np(m[g]).T, m0, rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(to_np(v[g]).T, v0, rtol=1e-5, atol=1e-9)
 
 
 def test_sparse_adam_leaves_inactive_rows_bitwise():
     rng = np.random.default_rng(10)
     n = 3000
     rows = np.sort(rng.choice(n, size=300, replace=False))
-    params = {g: torch.tensor(rng.normal(size=(c, n)), dtype=torch.float32, device=DEV) for g, c in O.GROUPS}
-    m = {g: torch.zeros((c, n), device=DEV) for g, c in O.GROUPS}
-    v = {g: torch.zeros((c, n), device=DEV) for g, c in O.GROUPS}
+    params = params_to_device({g: rng.normal(size=(c, n)) for g, c in O.GROUPS})
+    m = {g: torch.zeros((n, c), device=DEV) for g, c in O.GROUPS}
+    v = {g: torch.zeros((n, c), device=DEV) for g, c in O.GROUPS}
     before = {g: params[g].clone() for g, _ in O.GROUPS}
     grads = {g: torch.ones((c, 300), device=DEV) for g, c in O.GROUPS}
     idx = torch.tensor(rows, dtype=torch.int32, device=DEV)
@@ -302,9 +303,9 @@ def test_sparse_adam_leaves_inactive_rows_bitwise():
     torch.cuda.synchronize()
     keep = torch.tensor(np.setdiff1d(np.arange(n), rows), device=DEV)
     for g, _ in O.GROUPS:
-        assert torch.equal(params[g][:, keep], before[g][:, keep])
-        assert torch.equal(m[g][:, keep], torch.zeros_like(m[g][:, keep]))
-        assert not torch.equal(params[g][:, idx.long()], before[g][:, idx.long()])
+        assert torch.equal(params[g][keep], before[g][keep])
+        assert torch.equal(m[g][keep], torch.zeros_like(m[g][keep]))
+        assert not torch.equal(params[g][idx.long()], before[g][idx.long()])
 
 
 def test_active_set_render_equals_dense():
@@ -373,6 +374,7 @@ def test_active_set_render_equals_dense():
             "delta_idx": torch.tensor(didx2, dtype=torch.int32, device=DEV),
             "delta_sign": torch.tensor(dsg2, dtype=torch.int8, device=DEV),
             "n_delta": torch.tensor([len(didx2)], dtype=torch.int32, device=DEV)}
+    pre_before = pre.clone()
     r2 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=16)
     r2.fit_pair_capacity(params, sigma, sc.background, act2, pre)
     r2.forward(params, sigma, sc.background, act2, pre)
@@ -382,6 +384,14 @@ def test_active_set_render_equals_dense():
         err = compare_image(imgs2[v], dense["image"], dense["near"])
         log(f"  after label changes, view {v}: err {err:.2e}")
         assert err <= IMAGE_RTOL
+    # the same pass from a pair capacity far too small through forward_fitted: the lists
+    # overflow, the capacity grows, the pre buffer gets its label changes exactly once
+    r3 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=16, pair_capacity=100)
+    r3.forward_fitted(params, sigma, sc.background, act2, pre_before)
+    torch.cuda.synchronize()
+    assert r3.tuning.pair_capacity > 100 and r3.status() == 0
+    assert torch.equal(r3.image, r2.image)
+    assert torch.equal(pre_before, pre)
 
 
 def test_pair_overflow_is_reported_and_bounded():
@@ -447,7 +457,7 @@ def test_autograd_matches_oracle_finite_differences():
 
     checked = 0
     for name, ncomp in O.GROUPS:
-        an = to_np(params[name].grad)
+        an = to_np(params[name].grad).T      # [n][C] -> [C][n]
         picks = [(c, i) for c in range(ncomp) for i in range(sc.n)]
         rng.shuffle(picks)
         num = den = 0.0

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     from paper_2605_13855_amd import oit
-    from paper_2605_13855_amd.render import _aligned_workspace
+    from paper_2605_13855_amd.render import _aligned_workspace, params_to_host
     from paper_2605_13855_amd.schedule import PaperScheduleTrainer
 
 DEV = "cuda"
@@ -101,7 +101,7 @@ def test_schedule_lazy_pre_buffers_match_dense_oracle():
     torch.cuda.synchronize()
     log(f"  epoch {t.epoch}, active {t.active_fraction():.3f}, rebuilds {t.rebuilds}, view epochs {t.view_epoch}")
     assert t.epoch >= 3
-    params = {g: to_np(p).astype(np.float32) for g, p in t.params.items()}
+    params = params_to_host(t.params)
     sigma = float(t.sigma.item())
     for v, cam in enumerate(sc.cameras):
         t.render_view(v)
