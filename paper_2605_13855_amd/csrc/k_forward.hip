@@ -505,6 +505,17 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
     const Rec r = a.b.rec[ri];
     const float tau = tile_tau(r.b.y);
     const uint32_t cls = sign == 0 ? 0u : 1u;
+    // half-extents of the widened alpha >= 1/255 box (the backward's, same formulas)
+    float hx = -1.f, hy = -1.f;
+    {
+        const float A = -r.a.z, B = -0.5f * r.a.w, C = -r.b.x;
+        const float det = A * C - B * B;
+        const float tb = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
+        if (tb > 0.f && det > 0.f) {
+            hx = sqrtf(tb * C / det) + 0.01f;
+            hy = sqrtf(tb * A / det) + 0.01f;
+        }
+    }
     const bool zero_ep = sign == 0 && a.b.bwd_mode == OIT_BWD_PER_PIXEL;
     // the pair's k-th tile hit takes slot hoff + k (same tile order as the count)
     uint64_t o = a.b.hoff[pv];
@@ -513,7 +524,20 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
             if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
             if (o < cap) {
                 const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
-                a.b.keys[0][o] = tile * 2u + cls;
+                // size class: 3 log2 of the box's pixel count inside the tile, so that
+                // a 64-entry backward chunk holds footprints of similar size
+                uint32_t sc = 0;
+                if (hx >= 0.f) {
+                    const float dx0 = (float)(tx * S) + 0.5f - r.a.x, dy0 = (float)(ty * S) + 0.5f - r.a.y;
+                    const float lim = 1e6f;
+                    const int c0 = max(0, (int)ceilf(fmaxf(-hx - dx0, -lim)));
+                    const int c1 = min(min(S, cam.W - tx * S) - 1, (int)floorf(fminf(hx - dx0, lim)));
+                    const int r0 = max(0, (int)ceilf(fmaxf(-hy - dy0, -lim)));
+                    const int r1 = min(min(S, cam.H - ty * S) - 1, (int)floorf(fminf(hy - dy0, lim)));
+                    const int area = (c1 >= c0 && r1 >= r0) ? (c1 - c0 + 1) * (r1 - r0 + 1) : 0;
+                    if (area > 1) sc = min((1u << kSizeBits) - 1u, (uint32_t)(3.f * log2f((float)area)));
+                }
+                a.b.keys[0][o] = ((tile * 2u + cls) << kSizeBits) | sc;
                 a.b.vals[0][o] = (uint32_t)o;
                 a.b.recs[0][o] = (uint32_t)t;
                 if (zero_ep) {
@@ -629,8 +653,9 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint32_t *keys, const
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.T) return;
     const uint32_t n = *nptr;
-    const uint32_t s0 = lower_bound_u32(keys, n, 2u * t), s1 = lower_bound_u32(keys, n, 2u * t + 1u),
-                   s2 = lower_bound_u32(keys, n, 2u * t + 2u);
+    const uint32_t k0 = (2u * t) << kSizeBits, k1 = (2u * t + 1u) << kSizeBits, k2 = (2u * t + 2u) << kSizeBits;
+    const uint32_t s0 = lower_bound_u32(keys, n, k0), s1 = lower_bound_u32(keys, n, k1),
+                   s2 = lower_bound_u32(keys, n, k2);
     b.cnt_a[t] = s1 - s0;
     b.cnt_d[t] = s2 - s1;
 }
@@ -643,9 +668,10 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
     launch_scan_u32_dev(b.nhits, b.hoff, b.counters + CNT_NPAIRS, b.scan_tmp, s);
     hipLaunchKernelGGL(k_list_total, dim3(1), dim3(1), 0, s, la);
     hipLaunchKernelGGL(k_list, dim3(kRecBlocks), dim3(256), 0, s, la);
-    // keys are tile * 2 + class < 2 T: as many 8-bit digits as that needs (>= 1); the
-    // last pass writes the unsorted slots to `orig` and the records to `entries`
-    const uint32_t kmax = 2u * (uint32_t)b.T;
+    // keys are (tile * 2 + class) * 2^kSizeBits + size class < 2 T 2^kSizeBits: as many
+    // 8-bit digits as that needs (>= 1); the last pass writes the unsorted slots to
+    // `orig` and the records to `entries`
+    const uint32_t kmax = (2u * (uint32_t)b.T) << kSizeBits;
     int bits = 0;
     while (bits < 32 && (kmax >> bits) != 0) ++bits;
     const int passes = bits == 0 ? 1 : (bits + 7) / 8;

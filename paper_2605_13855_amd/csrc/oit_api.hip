@@ -146,7 +146,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
         d.pix_base = (int)px;
         tiles += (int64_t)d.tiles_x * d.tiles_y;
         px += (int64_t)c.width * c.height;
-        if (tiles > 0x7fffffffLL || px > 0x7fffffffLL / 9)
+        if (tiles > (0xffffffffLL >> (kSizeBits + 1)) || px > 0x7fffffffLL / 9)
             return fail(OIT_ERR_INVALID, "batch too large: %lld tiles, %lld pixels", (long long)tiles, (long long)px);
     }
     p.T = (int)tiles;

@@ -15,6 +15,7 @@ constexpr int kScanThreads = 1024;
 constexpr int kEpStride = 12;                  // floats per entry partial (10 used, 16-byte rows)
 constexpr int kScanBlockItems = 256 * 16;      // values per block of the device-wide scan
 constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (each a contiguous range)
+constexpr int kSizeBits = 5;                   // footprint-size class below (tile, class) in the sort key
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
@@ -58,7 +59,7 @@ struct Buffers {
     // Tile entries.  Every (listed record, view) pair -- index view * nrec + k for the
     // k-th listed record, nrec = listed records of the call -- owns the slots
     // [hoff, hoff + nhits) of the unsorted list, one per tile it reaches; the list is
-    // sorted by (tile, class) into `entries` (record index) and `orig` (the entry's
+    // sorted by (tile, class, size class) into `entries` (record index) and `orig` (the entry's
     // unsorted slot).
     uint32_t *entries;                          // [pair_cap]
     uint32_t *orig;                             // [pair_cap]
@@ -95,7 +96,7 @@ void fill_f64(double *p, size_t n, double v, hipStream_t s);
 void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const float *sigma, const RowList &rl,
                              const Buffers &b, hipStream_t s);
 void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
-// count scan, entry list, sort by (tile, class), per-tile ranges (after preprocess)
+// count scan, entry list, sort by (tile, class, size class), per-tile ranges (after preprocess)
 void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s);
 // Optional kernel timing: a launch given a KTimer records `start` when the kernel
 // begins and `stop` when it ends (hipExtLaunchKernelGGL; not for graph capture).
