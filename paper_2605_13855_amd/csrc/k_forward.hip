@@ -563,10 +563,13 @@ __global__ __launch_bounds__(256) void k_list(ListArgs a)
     }
 }
 
-// --- stable LSD radix sort of (key, value) pairs, 8-bit digits -----------------------
+// --- stable LSD radix sort of (key, value, record) triples, kRadixBits-bit digits ---
 // A fixed grid of kSortGrid blocks; block b sorts the contiguous range of the n keys
 // (n on the device) that sort_range gives it, so the work follows n, not the capacity,
-// and the block order is the key order (stability).
+// and the block order is the key order (stability).  The digit is narrow on purpose:
+// every (block, digit) pair has a partly written output line per array, and with 32
+// digits those lines (about 1.6 MB per XCD) stay in L2 until they are complete, where
+// 256 digits would have them evicted half written.
 __device__ __forceinline__ void sort_range(uint64_t n, uint64_t &lo, uint64_t &hi)
 {
     uint64_t chunk = (n + kSortGrid - 1) / kSortGrid;
@@ -580,14 +583,15 @@ __device__ __forceinline__ void sort_range(uint64_t n, uint64_t &lo, uint64_t &h
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const uint32_t *nptr, int shift,
                                                     uint32_t *hist)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[kRadixBuckets];
+    if (threadIdx.x < kRadixBuckets) h[threadIdx.x] = 0;
     __syncthreads();
     uint64_t lo, hi;
     sort_range(*nptr, lo, hi);
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256)
+        atomicAdd(&h[(keys[i] >> shift) & (kRadixBuckets - 1u)], 1u);
     __syncthreads();
-    hist[(size_t)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < kRadixBuckets) hist[(size_t)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
 }
 
 // Scatter each block's keys to their digit's range in key order: rounds of 256 keys in
@@ -598,11 +602,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
                                                        uint32_t *vals_out, uint32_t *recs_out, const uint32_t *nptr,
                                                        int shift, const uint32_t *hist_off)
 {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[4][256];
+    __shared__ uint32_t run[kRadixBuckets];
+    __shared__ uint32_t wc[4][kRadixBuckets];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
-    for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    if (tid < kRadixBuckets) {
+        run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
+        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+    }
     __syncthreads();
     uint64_t lo, hi;
     sort_range(*nptr, lo, hi);
@@ -611,10 +617,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
         const uint64_t i = base + tid;
         const bool valid = i < hi;
         const uint32_t key = valid ? keys_in[i] : 0u, val = valid ? vals_in[i] : 0u, rec = valid ? recs_in[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & (kRadixBuckets - 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
+        for (int bit = 0; bit < kRadixBits; ++bit) {
             const bool set = (d >> bit) & 1u;
             const uint64_t bb = __ballot(set);
             peers &= set ? bb : ~bb;
@@ -630,8 +636,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
             recs_out[pos] = rec;
         }
         __syncthreads();
-        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+        if (tid < kRadixBuckets) {
+            run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+            for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+        }
         __syncthreads();
     }
 }
@@ -669,23 +677,23 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
     hipLaunchKernelGGL(k_list_total, dim3(1), dim3(1), 0, s, la);
     hipLaunchKernelGGL(k_list, dim3(kRecBlocks), dim3(256), 0, s, la);
     // keys are (tile * 2 + class) * 2^kSizeBits + size class < 2 T 2^kSizeBits: as many
-    // 8-bit digits as that needs (>= 1); the last pass writes the unsorted slots to
-    // `orig` and the records to `entries`
+    // kRadixBits-bit digits as that needs (>= 1); the last pass writes the unsorted
+    // slots to `orig` and the records to `entries`
     const uint32_t kmax = (2u * (uint32_t)b.T) << kSizeBits;
     int bits = 0;
     while (bits < 32 && (kmax >> bits) != 0) ++bits;
-    const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+    const int passes = bits == 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
     const uint32_t *nptr = b.counters + CNT_SORT_N;
     int cur = 0;
     for (int ps = 0; ps < passes; ++ps) {
         const bool last = ps == passes - 1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur], nptr, 8 * ps,
-                           b.hist);
-        launch_scan_u32(b.hist, b.hist_off, 256 * (int64_t)kSortGrid, b.scan_tmp, s);
+        hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur], nptr,
+                           kRadixBits * ps, b.hist);
+        launch_scan_u32(b.hist, b.hist_off, kRadixBuckets * (int64_t)kSortGrid, b.scan_tmp, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur],
                            (const uint32_t *)b.vals[cur], (const uint32_t *)b.recs[cur], b.keys[cur ^ 1],
-                           last ? b.orig : b.vals[cur ^ 1], last ? b.entries : b.recs[cur ^ 1], nptr, 8 * ps,
-                           (const uint32_t *)b.hist_off);
+                           last ? b.orig : b.vals[cur ^ 1], last ? b.entries : b.recs[cur ^ 1], nptr,
+                           kRadixBits * ps, (const uint32_t *)b.hist_off);
         cur ^= 1;
     }
     hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)((b.T + 255) / 256)), dim3(256), 0, s,

@@ -173,14 +173,14 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.vals1 = o; o = align256(o + 4 * pc);
     p.recs0 = o; o = align256(o + 4 * pc);
     p.recs1 = o; o = align256(o + 4 * pc);
-    p.hist = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
-    p.hist_off = o; o = align256(o + 4 * 256 * (size_t)kSortGrid);
+    p.hist = o; o = align256(o + 4 * kRadixBuckets * (size_t)kSortGrid);
+    p.hist_off = o; o = align256(o + 4 * kRadixBuckets * (size_t)kSortGrid);
     p.rec = o; o = align256(o + sizeof(Rec) * (size_t)n_views * p.Rcap);
     p.rect = o; o = align256(o + sizeof(short4) * (size_t)n_views * p.Rcap);
     const size_t npairs = (size_t)n_views * p.Rcap;
     p.nhits = o; o = align256(o + 4 * npairs);
     p.hoff = o; o = align256(o + 4 * npairs);
-    const size_t nscan = npairs > 256 * (size_t)kSortGrid ? npairs : 256 * (size_t)kSortGrid;
+    const size_t nscan = npairs > kRadixBuckets * (size_t)kSortGrid ? npairs : kRadixBuckets * (size_t)kSortGrid;
     p.scan_tmp = o; o = align256(o + 4 * (nscan / kScanBlockItems + 2));
     p.ep = o; o = align256(o + 4 * kEpStride * pc);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);

@@ -15,6 +15,8 @@ constexpr int kScanThreads = 1024;
 constexpr int kEpStride = 12;                  // floats per entry partial (10 used, 16-byte rows)
 constexpr int kScanBlockItems = 256 * 16;      // values per block of the device-wide scan
 constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (each a contiguous range)
+constexpr int kRadixBits = 5;                  // digit width of a radix-sort pass
+constexpr int kRadixBuckets = 1 << kRadixBits;
 constexpr int kSizeBits = 5;                   // footprint-size class below (tile, class) in the sort key
 
 // counters[] slots in the workspace
@@ -64,7 +66,7 @@ struct Buffers {
     uint32_t *entries;                          // [pair_cap]
     uint32_t *orig;                             // [pair_cap]
     uint32_t *keys[2], *vals[2], *recs[2];      // [pair_cap] radix-sort buffers
-    uint32_t *hist, *hist_off;                  // [256][kSortGrid] digit counts and their scan
+    uint32_t *hist, *hist_off;                  // [kRadixBuckets][kSortGrid] digit counts and their scan
     Rec *rec;                                   // [V][Rcap]
     short4 *rect;                               // [V][Rcap] tile rectangle [x0, x1) x [y0, y1)
     uint32_t *nhits;                            // [pairs] tiles the (listed record, view) pair reaches
