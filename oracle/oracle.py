@@ -14,11 +14,15 @@ definition:
   text after it: a splat is active if at least one attribute group's gradient norm
   exceeds its threshold; top-k selection breaks ties by the lower index);
 * Adam on a subset of rows (Sec. 4.1, Alg. "Active Set Method": only the active
-  splats are updated; the optimiser is Adam, Sec. 5.1).
+  splats are updated; the optimiser is Adam, Sec. 5.1);
+* densification, pruning and the opacity reset of the first training phase (Sec. 5.1
+  "Implementation Details": 3DGS's density control with a random keep probability),
+  with the readings listed above their code.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -399,3 +403,145 @@ def l1_dssim_loss(image, target, lam=0.2):
     l1, g1 = l1_loss(image, target)
     ds, g2 = dssim_loss_grad(image, target)
     return (1 - lam) * l1 + lam * ds, (1 - lam) * g1 + lam * g2
+
+
+# ----------------------------------------------------------------------------------
+# Densification and pruning (numpy float64).  The paper trains its first phase as
+# 3DGS does, densification included, and keeps 3DGS's density control, adding a
+# scene-specific random keep probability that caps the splat count (Sec. 5.1
+# "Implementation Details"; Fig. "overview": the active-set phase starts after it).
+# The rules themselves are those of 3DGS's adaptive density control, which the paper
+# adopts without restating; the readings are:
+#   * statistic: per (splat, view) where the splat is visible, the norm of the loss
+#     gradient with respect to its projected mean expressed per normalised-device
+#     unit (pixel gradient times W / 2 and H / 2), summed over views, with the
+#     number of visible views and the largest 3-sigma screen radius;
+#   * visible: the projection is valid, opacity >= 1/255, and the footprint box of
+#     the alpha >= 1/255 ellipse contains at least one pixel centre of the image;
+#   * a splat is a candidate when its mean statistic reaches the threshold and its
+#     uniform draw is below the keep probability; a small candidate (largest scale
+#     <= percent_dense * extent) is cloned, a large one is replaced by two children
+#     drawn from its Gaussian (mean + R diag(s) z) with scales divided by 1.6;
+#   * pruning applies to the densified set: every splat below the minimum opacity,
+#     every splat whose largest scale exceeds max_world_frac * extent, and every
+#     original splat whose recorded screen radius exceeds max_screen_size;
+#   * order of the new set: surviving originals, then clone copies, then the first
+#     children of the split splats, then their second children, each in source order;
+#     new splats start with zero Adam moments.
+# ----------------------------------------------------------------------------------
+from dataclasses import dataclass  # noqa: E402
+
+SPLIT_DIVISOR = 1.6
+
+
+@dataclass
+class DensityRules:
+    grad_threshold: float = 0.0002
+    percent_dense: float = 0.01
+    scene_extent: float = 1.0
+    min_opacity: float = 0.005
+    max_screen_size: float = 0.0    # <= 0: off
+    max_world_frac: float = 0.0     # <= 0: off
+    keep_probability: float = 1.0
+
+
+def footprint_visible(pr_row, width, height):
+    """Whether a projected splat (a row of project()) reaches a pixel centre of the image."""
+    valid, mx, my, tau = pr_row[0], pr_row[1], pr_row[2], pr_row[13]
+    if not valid or tau < 0.0:
+        return False
+    hx, hy = math.sqrt(tau * pr_row[14]), math.sqrt(tau * pr_row[16])
+    x_lo, x_hi = math.ceil(mx - hx - 0.5), math.floor(mx + hx - 0.5)
+    y_lo, y_hi = math.ceil(my - hy - 0.5), math.floor(my + hy - 0.5)
+    return max(x_lo, 0) <= min(x_hi, width - 1) and max(y_lo, 0) <= min(y_hi, height - 1)
+
+
+def screen_radius(pr_row):
+    """3 sigma of the major axis of the screen covariance (pixels)."""
+    a, b, c = pr_row[14], pr_row[15], pr_row[16]
+    lam = 0.5 * (a + c) + math.sqrt(0.25 * (a - c) ** 2 + b * b)
+    return 3.0 * math.sqrt(lam)
+
+
+def densify_stats(params, sigma, bg, cams, dLdCs, accum=None, denom=None, max_radius=None):
+    """Accumulate the densification statistic over the views (dLdCs[k] [3][H][W])."""
+    n = params["mean"].shape[1]
+    accum = np.zeros(n) if accum is None else accum
+    denom = np.zeros(n) if denom is None else denom
+    max_radius = np.zeros(n) if max_radius is None else max_radius
+    for cam, g in zip(cams, dLdCs):
+        pr = project(params, sigma, cam)
+        _, _, scr = backward(params, sigma, bg, cam, g, screen=True)
+        for i in range(n):
+            if not footprint_visible(pr[i], cam.width, cam.height):
+                continue
+            accum[i] += math.hypot(scr[i, 0] * cam.width / 2.0, scr[i, 1] * cam.height / 2.0)
+            denom[i] += 1.0
+            max_radius[i] = max(max_radius[i], screen_radius(pr[i]))
+    return accum, denom, max_radius
+
+
+def densify_decisions(params, accum, denom, max_radius, uniform, rules: DensityRules):
+    """Per splat: (clone, split, keep_original, keep_clone, keep_children) boolean arrays."""
+    avg = np.where(denom > 0, accum / np.where(denom > 0, denom, 1.0), 0.0)
+    cand = (avg >= rules.grad_threshold) & (np.asarray(uniform) < rules.keep_probability)
+    smax = np.exp(params["log_scale"]).max(axis=0)
+    small = smax <= rules.percent_dense * rules.scene_extent
+    clone, split = cand & small, cand & ~small
+    low = 1.0 / (1.0 + np.exp(-params["opacity_logit"][0])) < rules.min_opacity
+
+    def world_big(s):
+        return (s > rules.max_world_frac * rules.scene_extent) if rules.max_world_frac > 0 else np.zeros_like(s, bool)
+
+    screen_big = (max_radius > rules.max_screen_size) if rules.max_screen_size > 0 else np.zeros(len(smax), bool)
+    keep_orig = ~split & ~low & ~screen_big & ~world_big(smax)
+    keep_clone = clone & ~low & ~world_big(smax)
+    keep_children = split & ~low & ~world_big(smax / SPLIT_DIVISOR)
+    return clone, split, keep_orig, keep_clone, keep_children
+
+
+def split_child(params, i, z):
+    """Parameters of a child of splat i for the standard normal draw z [3]."""
+    q = params["quat"][:, i] / np.linalg.norm(params["quat"][:, i])
+    R = quat_to_rot(q)
+    s = np.exp(params["log_scale"][:, i])
+    child = {g: params[g][:, i].copy() for g, _ in GROUPS}
+    child["mean"] = params["mean"][:, i] + R @ (s * np.asarray(z, np.float64))
+    child["log_scale"] = params["log_scale"][:, i] - math.log(SPLIT_DIVISOR)
+    return child
+
+
+def densify(params, m, v, accum, denom, max_radius, uniform, normals, rules: DensityRules):
+    """The densified and pruned set: (params, m, v, source) with source[j] the splat
+    that new splat j comes from.  normals [n][2][3]: the draws of the two children."""
+    clone, split, keep_orig, keep_clone, keep_children = densify_decisions(
+        params, accum, denom, max_radius, uniform, rules)
+    cols, src, fresh = [], [], []
+    for i in np.flatnonzero(keep_orig):
+        cols.append({g: params[g][:, i] for g, _ in GROUPS}); src.append(i); fresh.append(False)
+    for i in np.flatnonzero(keep_clone):
+        cols.append({g: params[g][:, i] for g, _ in GROUPS}); src.append(i); fresh.append(True)
+    for k in range(2):
+        for i in np.flatnonzero(keep_children):
+            cols.append(split_child(params, i, normals[i][k])); src.append(i); fresh.append(True)
+    n_new = len(cols)
+    out_p = {g: np.zeros((c, n_new)) for g, c in GROUPS}
+    out_m = {g: np.zeros((c, n_new)) for g, c in GROUPS}
+    out_v = {g: np.zeros((c, n_new)) for g, c in GROUPS}
+    for j, col in enumerate(cols):
+        for g, _ in GROUPS:
+            out_p[g][:, j] = col[g]
+            if not fresh[j]:
+                out_m[g][:, j] = m[g][:, src[j]]
+                out_v[g][:, j] = v[g][:, src[j]]
+    return out_p, out_m, out_v, np.asarray(src, np.int64)
+
+
+def reset_opacity(params, m, v, max_opacity=0.01):
+    """Opacity reset of 3DGS: every opacity is clamped to max_opacity and the opacity
+    group's Adam moments restart from zero."""
+    cap = math.log(max_opacity / (1.0 - max_opacity))
+    params["opacity_logit"] = np.minimum(params["opacity_logit"], cap)
+    m["opacity_logit"] = np.zeros_like(m["opacity_logit"])
+    v["opacity_logit"] = np.zeros_like(v["opacity_logit"])
+    return params, m, v
