@@ -419,7 +419,8 @@ def l1_dssim_loss(image, target, lam=0.2):
 #   * visible: the projection is valid, opacity >= 1/255, and the footprint box of
 #     the alpha >= 1/255 ellipse contains at least one pixel centre of the image;
 #   * a splat is a candidate when its mean statistic reaches the threshold and its
-#     uniform draw is below the keep probability; a small candidate (largest scale
+#     uniform draw is below the keep probability (these comparisons, which decide what
+#     exists, in float32: the kernels' precision); a small candidate (largest scale
 #     <= percent_dense * extent) is cloned, a large one is replaced by two children
 #     drawn from its Gaussian (mean + R diag(s) z) with scales divided by 1.6;
 #   * pruning applies to the densified set: every splat below the minimum opacity,
@@ -482,21 +483,28 @@ def densify_stats(params, sigma, bg, cams, dLdCs, accum=None, denom=None, max_ra
 
 
 def densify_decisions(params, accum, denom, max_radius, uniform, rules: DensityRules):
-    """Per splat: (clone, split, keep_original, keep_clone, keep_children) boolean arrays."""
-    avg = np.where(denom > 0, accum / np.where(denom > 0, denom, 1.0), 0.0)
-    cand = (avg >= rules.grad_threshold) & (np.asarray(uniform) < rules.keep_probability)
-    smax = np.exp(params["log_scale"]).max(axis=0)
-    small = smax <= rules.percent_dense * rules.scene_extent
+    """Per splat: (clone, split, keep_original, keep_clone, keep_children) boolean arrays.
+    These comparisons decide integers (which splats exist), so they are taken in float32,
+    the kernels' precision (the paper fixes none)."""
+    f = np.float32
+    accum, denom = np.asarray(accum, f), np.asarray(denom, f)
+    avg = np.where(denom > 0, accum / np.where(denom > 0, denom, f(1)), f(0))
+    cand = (avg >= f(rules.grad_threshold)) & (np.asarray(uniform, f) < f(rules.keep_probability))
+    smax = np.exp(np.asarray(params["log_scale"], f)).max(axis=0)
+    small = smax <= f(rules.percent_dense) * f(rules.scene_extent)
     clone, split = cand & small, cand & ~small
-    low = 1.0 / (1.0 + np.exp(-params["opacity_logit"][0])) < rules.min_opacity
+    low = f(1) / (f(1) + np.exp(-np.asarray(params["opacity_logit"][0], f))) < f(rules.min_opacity)
 
     def world_big(s):
-        return (s > rules.max_world_frac * rules.scene_extent) if rules.max_world_frac > 0 else np.zeros_like(s, bool)
+        if rules.max_world_frac <= 0:
+            return np.zeros(s.shape, bool)
+        return s > f(rules.max_world_frac) * f(rules.scene_extent)
 
-    screen_big = (max_radius > rules.max_screen_size) if rules.max_screen_size > 0 else np.zeros(len(smax), bool)
+    screen_big = (np.asarray(max_radius, f) > f(rules.max_screen_size)) if rules.max_screen_size > 0 \
+        else np.zeros(len(smax), bool)
     keep_orig = ~split & ~low & ~screen_big & ~world_big(smax)
     keep_clone = clone & ~low & ~world_big(smax)
-    keep_children = split & ~low & ~world_big(smax / SPLIT_DIVISOR)
+    keep_children = split & ~low & ~world_big(smax / f(SPLIT_DIVISOR))
     return clone, split, keep_orig, keep_clone, keep_children
 
 
