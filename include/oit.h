@@ -294,6 +294,87 @@ oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m,
                                float lr, float beta1, float beta2, float eps, int32_t *step,
                                oit_stream stream);
 
+/* ---------------------------------------------------------------------------------
+ * Densification and pruning of the first training phase.  The paper trains its first
+ * 15,000 iterations as 3DGS does, with 3DGS's density control plus a random keep
+ * probability that caps the splat count, and starts the active-set phase after it
+ * (Sec. 5.1 "Implementation Details"; Fig. "overview").  The rules are 3DGS's:
+ *   statistic  per (splat, view) where the splat is visible (valid projection, opacity
+ *              >= 1/255, the box of its alpha >= 1/255 ellipse reaches a pixel centre
+ *              of the image): the norm of dL/d(projected mean) per normalised-device
+ *              unit, (dL/dmx W/2, dL/dmy H/2), summed into grad_accum; denom counts
+ *              those views; max_radius keeps the largest 3-sigma screen radius (px);
+ *   candidate  grad_accum / denom >= grad_threshold and the splat's uniform draw <
+ *              keep_probability; a candidate whose largest scale is <= percent_dense *
+ *              scene_extent is cloned, a larger one is replaced by two children at
+ *              mean + R diag(s) z (z a standard normal draw per child) with every
+ *              scale divided by 1.6;
+ *   pruning    of the densified set: opacity < min_opacity; largest scale >
+ *              max_world_frac * scene_extent (if max_world_frac > 0); for original
+ *              splats, max_radius > max_screen_size (if max_screen_size > 0);
+ *   order      surviving originals, clone copies, first children, second children,
+ *              each in source order; new splats get zero Adam moments.
+ * These decisions are taken in float32.
+ * --------------------------------------------------------------------------------- */
+typedef struct {
+    float grad_threshold;   /* 3DGS: 0.0002 */
+    float percent_dense;    /* 3DGS: 0.01 */
+    float scene_extent;     /* > 0 */
+    float min_opacity;      /* 3DGS: 0.005 */
+    float max_screen_size;  /* pixels; <= 0 disables (3DGS: 20 after the first opacity reset) */
+    float max_world_frac;   /* <= 0 disables (3DGS: 0.1 with the screen-size rule) */
+    float keep_probability; /* in [0, 1]: the paper's random sampling of densification */
+    int32_t reserved;       /* 0 */
+} oit_density_rules;        /* (host) */
+
+/*
+ * Add the densification statistic of the last oit_render_bwd to grad_accum, denom and
+ * max_radius (each [n] float, indexed by splat id; the caller zeroes them when a
+ * densification interval starts).  Call it after oit_render_bwd, on the same stream,
+ * with the same cams, capacity, active rows and tuning and the same workspace, before
+ * the workspace is used again: it reads the records and the per-entry partials that
+ * call left there.  Rows are the active rows of that call (all splats in dense mode).
+ * Returns OIT_ERR_INVALID for NULL accumulators or bad sizes; nothing is enqueued then.
+ */
+oit_status oit_densify_stats(const oit_camera *cams, int32_t n_views, const oit_capacity *cap,
+                             const int32_t *active_idx, const int32_t *n_active, const int32_t *n_delta,
+                             float *grad_accum, float *denom, float *max_radius,
+                             const void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream);
+
+/* Workspace bytes of oit_densify_plan / oit_densify_apply for n splats. */
+size_t oit_densify_workspace_bytes(int64_t n);
+
+/*
+ * Decide, for every splat, whether it is kept, cloned or split and which of the
+ * results survive pruning (rules above), and write the size of the new set to
+ * *n_new (device int64).  uniform [n]: the splats' uniform draws in [0, 1).  The
+ * decisions stay in the workspace for oit_densify_apply.
+ */
+oit_status oit_densify_plan(const oit_splats *splats, const float *grad_accum, const float *denom,
+                            const float *max_radius, const float *uniform, const oit_density_rules *rules,
+                            int64_t *n_new, void *ws, size_t ws_bytes, oit_stream stream);
+
+/*
+ * Write the new set planned by the last oit_densify_plan on this workspace (same
+ * splats): params_new, m_new and v_new are [6] pointers to [cap_new][C] groups in the
+ * order of oit_splats (mean, log_scale, quat, opacity_logit, sh, vsh); m / v are the
+ * old moments.  normals [n][2][3]: the standard normal draws of each splat's two
+ * children (read for split splats only).  Rows at or past cap_new are not written, so
+ * the caller reads *n_new first and passes cap_new >= it.
+ */
+oit_status oit_densify_apply(const oit_splats *splats, const float *const *m, const float *const *v,
+                             const float *normals, float *const *params_new, float *const *m_new,
+                             float *const *v_new, int64_t cap_new, const void *ws, size_t ws_bytes,
+                             oit_stream stream);
+
+/*
+ * 3DGS's opacity reset: every opacity above max_opacity is set to it (logit clamped to
+ * log(max_opacity / (1 - max_opacity))) and the opacity group's Adam moments restart
+ * from zero.  opacity_logit, m_opacity, v_opacity [n].
+ */
+oit_status oit_reset_opacity(float *opacity_logit, float *m_opacity, float *v_opacity, int64_t n,
+                             float max_opacity, oit_stream stream);
+
 /* Wait for `stream` and copy the workspace's device status word to *out (host). */
 oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream);
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "liboit.so")
-SOURCES = ["oit_api.hip", "k_forward.hip", "k_backward.hip", "k_select.hip", "k_adam.hip", "k_loss.hip"]
+SOURCES = ["oit_api.hip", "k_forward.hip", "k_backward.hip", "k_select.hip", "k_adam.hip", "k_loss.hip", "k_density.hip"]
 ARCH = os.environ.get("OIT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

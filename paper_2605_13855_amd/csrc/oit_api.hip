@@ -7,6 +7,7 @@
 #include <cstring>
 #include <vector>
 
+#include "oit_density.h"
 #include "oit_internal.h"
 
 using namespace oit;
@@ -596,6 +597,101 @@ oit_status oit_sigma_adam_step(float *sigma, const double *grad_sigma, float *m,
     if (!sigma || !grad_sigma || !m || !v || !step) return fail(OIT_ERR_INVALID, "oit_sigma_adam_step: NULL argument");
     launch_sigma_adam(sigma, grad_sigma, m, v, lr, beta1, beta2, eps, step, (hipStream_t)stream);
     return check_launch("oit_sigma_adam_step");
+}
+
+// ---------------------------------------------------------------------------------
+// densification of the first training phase (k_density.hip)
+// ---------------------------------------------------------------------------------
+oit_status oit_densify_stats(const oit_camera *cams, int32_t n_views, const oit_capacity *cap,
+                             const int32_t *active_idx, const int32_t *n_active, const int32_t *n_delta,
+                             float *grad_accum, float *denom, float *max_radius, const void *ws, size_t ws_bytes,
+                             const oit_tuning *tuning, oit_stream stream)
+{
+    Plan p;
+    oit_status st;
+    if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
+    if (!grad_accum || !denom || !max_radius) return fail(OIT_ERR_INVALID, "grad_accum, denom and max_radius are required");
+    if (!active_idx && (n_active || n_delta || cap->active_capacity != cap->n))
+        return fail(OIT_ERR_INVALID, "dense mode takes no n_active or n_delta and needs active_capacity == n");
+    if (active_idx && !n_active) return fail(OIT_ERR_INVALID, "active_idx given without n_active");
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < p.total) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+    const Buffers b = buffers(p, const_cast<void *>(ws), n_views, tuning);
+    const RowList rl = rows(cap, active_idx, n_active, nullptr, nullptr, n_delta, p);
+    launch_densify_stats(b, rl, grad_accum, denom, max_radius, (hipStream_t)stream);
+    return check_launch("oit_densify_stats");
+}
+
+size_t oit_densify_workspace_bytes(int64_t n)
+{
+    return n > 0 ? density_workspace_bytes(n) : 0;
+}
+
+namespace {
+oit_status check_density_splats(const oit_splats *s)
+{
+    if (!s) return fail(OIT_ERR_INVALID, "splats is NULL");
+    if (s->n <= 0 || s->n > 0x7fffffffLL) return fail(OIT_ERR_INVALID, "splats.n = %lld outside [1, 2^31)", (long long)s->n);
+    const void *ptrs[6] = {s->mean, s->log_scale, s->quat, s->opacity_logit, s->sh, s->vsh};
+    for (int k = 0; k < 6; ++k)
+        if (!ptrs[k] || !aligned(ptrs[k], 4)) return fail(OIT_ERR_INVALID, "splat group %d NULL or misaligned", k);
+    return OIT_OK;
+}
+
+oit_status check_density_ws(const void *ws, size_t ws_bytes, int64_t n)
+{
+    if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    const size_t need = density_workspace_bytes(n);
+    if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return OIT_OK;
+}
+}  // namespace
+
+oit_status oit_densify_plan(const oit_splats *splats, const float *grad_accum, const float *denom,
+                            const float *max_radius, const float *uniform, const oit_density_rules *rules,
+                            int64_t *n_new, void *ws, size_t ws_bytes, oit_stream stream)
+{
+    oit_status st;
+    if ((st = check_density_splats(splats)) != OIT_OK) return st;
+    if (!grad_accum || !denom || !max_radius || !uniform || !rules || !n_new)
+        return fail(OIT_ERR_INVALID, "oit_densify_plan: NULL argument");
+    if (!aligned(n_new, 8)) return fail(OIT_ERR_INVALID, "n_new must be 8-byte aligned");
+    if (!(rules->scene_extent > 0.f) || !(rules->keep_probability >= 0.f && rules->keep_probability <= 1.f) ||
+        !(rules->percent_dense >= 0.f) || rules->reserved != 0)
+        return fail(OIT_ERR_INVALID, "bad density rules (scene_extent > 0, keep_probability in [0, 1], reserved 0)");
+    if ((st = check_density_ws(ws, ws_bytes, splats->n)) != OIT_OK) return st;
+    launch_densify_plan(splat_ptrs(splats), grad_accum, denom, max_radius, uniform, *rules, n_new,
+                        density_buffers(ws, splats->n), (hipStream_t)stream);
+    return check_launch("oit_densify_plan");
+}
+
+oit_status oit_densify_apply(const oit_splats *splats, const float *const *m, const float *const *v,
+                             const float *normals, float *const *params_new, float *const *m_new,
+                             float *const *v_new, int64_t cap_new, const void *ws, size_t ws_bytes,
+                             oit_stream stream)
+{
+    oit_status st;
+    if ((st = check_density_splats(splats)) != OIT_OK) return st;
+    if (!m || !v || !normals || !params_new || !m_new || !v_new) return fail(OIT_ERR_INVALID, "oit_densify_apply: NULL argument");
+    for (int k = 0; k < 6; ++k)
+        if (!m[k] || !v[k] || !params_new[k] || !m_new[k] || !v_new[k])
+            return fail(OIT_ERR_INVALID, "group %d: NULL pointer", k);
+    if (cap_new < 0) return fail(OIT_ERR_INVALID, "cap_new < 0");
+    if ((st = check_density_ws(ws, ws_bytes, splats->n)) != OIT_OK) return st;
+    launch_densify_apply(splat_ptrs(splats), m, v, normals, params_new, m_new, v_new, cap_new,
+                         density_buffers(const_cast<void *>(ws), splats->n), (hipStream_t)stream);
+    return check_launch("oit_densify_apply");
+}
+
+oit_status oit_reset_opacity(float *opacity_logit, float *m_opacity, float *v_opacity, int64_t n, float max_opacity,
+                             oit_stream stream)
+{
+    if (!opacity_logit || !m_opacity || !v_opacity) return fail(OIT_ERR_INVALID, "oit_reset_opacity: NULL argument");
+    if (n <= 0) return fail(OIT_ERR_INVALID, "n = %lld must be > 0", (long long)n);
+    if (!(max_opacity > 0.f && max_opacity < 1.f)) return fail(OIT_ERR_INVALID, "max_opacity must be in (0, 1)");
+    const float max_logit = (float)std::log((double)max_opacity / (1.0 - (double)max_opacity));
+    launch_reset_opacity(opacity_logit, m_opacity, v_opacity, n, max_logit, (hipStream_t)stream);
+    return check_launch("oit_reset_opacity");
 }
 
 oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_stream stream)

@@ -84,6 +84,12 @@ def _load():
     L.oit_l1_dssim_loss.restype = ctypes.c_int
     L.oit_label_delta.argtypes = [P, P, I64, P, I64, P, P, P, I64, P, P, SZ, P]
     L.oit_fps_views.argtypes = [P, I32, I32, I32, P]
+    L.oit_densify_stats.argtypes = [P, I32, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.oit_densify_workspace_bytes.argtypes = [I64]
+    L.oit_densify_workspace_bytes.restype = SZ
+    L.oit_densify_plan.argtypes = [P, P, P, P, P, P, P, P, SZ, P]
+    L.oit_densify_apply.argtypes = [P, P, P, P, P, P, P, I64, P, SZ, P]
+    L.oit_reset_opacity.argtypes = [P, P, P, I64, F, P]
     L.oit_timing_enable.argtypes = [I32]
     L.oit_timing_read.argtypes = [P]
     L.oit_last_error.argtypes = []
@@ -91,7 +97,8 @@ def _load():
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
               L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_label_delta,
-              L.oit_fps_views):
+              L.oit_fps_views, L.oit_densify_stats, L.oit_densify_plan, L.oit_densify_apply,
+              L.oit_reset_opacity):
         f.restype = ctypes.c_int
     return L
 
@@ -279,3 +286,48 @@ def timing_read():
 def clear_status(ws, stream=None):
     rc = lib.oit_clear_status(_ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "oit_clear_status")
+
+
+# ----------------------------------------------------------------------------------
+# densification of the first training phase
+# ----------------------------------------------------------------------------------
+class DensityRules(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("percent_dense", ctypes.c_float),
+                ("scene_extent", ctypes.c_float), ("min_opacity", ctypes.c_float),
+                ("max_screen_size", ctypes.c_float), ("max_world_frac", ctypes.c_float),
+                ("keep_probability", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+def densify_stats(cams_arr, n_views, cap: Capacity, active_idx, n_active, n_delta, grad_accum, denom, max_radius,
+                  ws, tuning: Tuning, stream=None):
+    rc = lib.oit_densify_stats(cams_arr, n_views, ctypes.byref(cap), _ptr(active_idx), _ptr(n_active),
+                               _ptr(n_delta), _ptr(grad_accum), _ptr(denom), _ptr(max_radius), _ptr(ws),
+                               ws.numel(), ctypes.byref(tuning), _stream(stream))
+    _check(rc, "oit_densify_stats")
+
+
+def densify_workspace_bytes(n: int) -> int:
+    return int(lib.oit_densify_workspace_bytes(int(n)))
+
+
+def densify_plan(splats: Splats, grad_accum, denom, max_radius, uniform, rules: DensityRules, n_new, ws,
+                 stream=None):
+    rc = lib.oit_densify_plan(ctypes.byref(splats), _ptr(grad_accum), _ptr(denom), _ptr(max_radius),
+                              _ptr(uniform), ctypes.byref(rules), _ptr(n_new), _ptr(ws), ws.numel(),
+                              _stream(stream))
+    _check(rc, "oit_densify_plan")
+
+
+def densify_apply(splats: Splats, m: dict, v: dict, normals, params_new: dict, m_new: dict, v_new: dict,
+                  cap_new: int, ws, stream=None):
+    P6 = ctypes.c_void_p * 6
+    arr = lambda d: P6(*[d[g].data_ptr() for g, _ in GROUPS])
+    rc = lib.oit_densify_apply(ctypes.byref(splats), arr(m), arr(v), _ptr(normals), arr(params_new), arr(m_new),
+                               arr(v_new), int(cap_new), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "oit_densify_apply")
+
+
+def reset_opacity(opacity_logit, m_opacity, v_opacity, n, max_opacity, stream=None):
+    rc = lib.oit_reset_opacity(_ptr(opacity_logit), _ptr(m_opacity), _ptr(v_opacity), int(n), float(max_opacity),
+                               _stream(stream))
+    _check(rc, "oit_reset_opacity")

@@ -82,3 +82,36 @@ def test_host_api_compiles_without_warnings():
     assert r.returncode == 0, r.stderr
     bad = [ln for ln in (r.stdout + r.stderr).splitlines() if "warning:" in ln and not B._benign(ln)]
     assert not bad, bad
+
+
+def test_density_entry_points_validate_on_host(lib):
+    """The densification calls reject bad arguments before any device work."""
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd import scenes
+    assert oit.densify_workspace_bytes(0) == 0
+    assert oit.densify_workspace_bytes(1000) >= 6 * 4000
+    cam = scenes.look_at_camera((0, 0, -3), 64, 48)
+    cams = oit.camera_array([cam])
+    cap = oit.Capacity(100, 100, 0)
+    tu = oit.Tuning(16, 64, 1000)
+    fake = ctypes.c_void_p(4096)
+    # no accumulators
+    assert oit.lib.oit_densify_stats(cams, 1, ctypes.byref(cap), None, None, None, None, None, None, fake, 1 << 30,
+                                     ctypes.byref(tu), None) == -1
+    # dense mode with a device count
+    assert oit.lib.oit_densify_stats(cams, 1, ctypes.byref(cap), None, fake, None, fake, fake, fake, fake, 1 << 30,
+                                     ctypes.byref(tu), None) == -1
+    assert oit.lib.oit_densify_plan(None, None, None, None, None, None, None, None, 0, None) == -1
+    sp = oit.Splats(100, *([4096] * 6))
+    bad = oit.DensityRules(2e-4, 0.01, 0.0, 0.005, 0.0, 0.0, 1.0, 0)       # extent 0
+    assert oit.lib.oit_densify_plan(ctypes.byref(sp), fake, fake, fake, fake, ctypes.byref(bad), fake, fake,
+                                    1 << 30, None) == -1
+    assert b"rules" in oit.lib.oit_last_error()
+    ok_rules = oit.DensityRules(2e-4, 0.01, 1.0, 0.005, 0.0, 0.0, 1.0, 0)
+    assert oit.lib.oit_densify_plan(ctypes.byref(sp), fake, fake, fake, fake, ctypes.byref(ok_rules), fake, fake,
+                                    16, None) == -4                              # workspace too small
+    P6 = ctypes.c_void_p * 6
+    six = P6(*([4096] * 6))
+    assert oit.lib.oit_densify_apply(ctypes.byref(sp), six, six, None, six, six, six, 10, fake, 1 << 30, None) == -1
+    assert oit.lib.oit_reset_opacity(None, None, None, 10, 0.01, None) == -1
+    assert oit.lib.oit_reset_opacity(fake, fake, fake, 10, 1.5, None) == -1
