@@ -491,7 +491,10 @@ __global__ void k_list_total(ListArgs a)
     if (E > cap) atomicOr(a.b.status, OIT_STATUS_PAIR_OVERFLOW);
 }
 
-__device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
+// STAGED: the entries go to the wave's LDS slice at (slot - base) and the wave writes
+// them out afterwards; otherwise straight to the list.
+template <bool STAGED>
+__device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv, uint32_t *sk, uint32_t *sr, uint64_t base)
 {
     int sign = 0;
     if (record_row(a.rl, t, sign) < 0) return;
@@ -524,6 +527,7 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
             if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
             if (o < cap) {
                 const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
+                uint32_t key;
                 // size class: 3 log2 of the box's pixel count inside the tile, so that
                 // a 64-entry backward chunk holds footprints of similar size
                 uint32_t sc = 0;
@@ -537,29 +541,64 @@ __device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv)
                     const int area = (c1 >= c0 && r1 >= r0) ? (c1 - c0 + 1) * (r1 - r0 + 1) : 0;
                     if (area > 1) sc = min((1u << kSizeBits) - 1u, (uint32_t)(3.f * log2f((float)area)));
                 }
-                a.b.keys[0][o] = ((tile * 2u + cls) << kSizeBits) | sc;
-                a.b.vals[0][o] = (uint32_t)o;
-                a.b.recs[0][o] = (uint32_t)t;
-                if (zero_ep) {
-                    float4 *e = (float4 *)(a.b.ep + o * kEpStride);
-                    e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                key = ((tile * 2u + cls) << kSizeBits) | sc;
+                if constexpr (STAGED) {
+                    sk[o - base] = key;
+                    sr[o - base] = (uint32_t)t;
+                } else {
+                    a.b.keys[0][o] = key;
+                    a.b.vals[0][o] = (uint32_t)o;
+                    a.b.recs[0][o] = (uint32_t)t;
+                    if (zero_ep) {
+                        float4 *e = (float4 *)(a.b.ep + o * kEpStride);
+                        e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
             }
             ++o;
         }
 }
 
-// view-major items: consecutive lanes take consecutive records of one view, whose
-// slots are adjacent in the unsorted list
+// View-major items: the 64 lanes of a wave take 64 consecutive (record, view) pairs,
+// whose slots form one contiguous range.  When the range fits the wave's LDS slice,
+// the lanes put their entries there and the wave writes the range out in order (one
+// 256-byte run per store instead of 64 scattered words); a larger range is written
+// directly.
+constexpr int kListStage = 1024;
+
 __global__ __launch_bounds__(256) void k_list(ListArgs a)
 {
+    __shared__ uint32_t s_key[4][kListStage], s_rec[4][kListStage];
     const int V = a.b.n_views;
     const RecItems it = rec_items(a.rl, V);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < it.total; i += stride) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t cap = (uint64_t)a.b.pair_cap;
+    const bool per_pixel = a.b.bwd_mode == OIT_BWD_PER_PIXEL;
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 64; i0 < it.total; i0 += (int64_t)gridDim.x * 256) {
+        const int64_t i = i0 + lane;
+        const int64_t last = i0 + 63 < it.total ? i0 + 63 : it.total - 1;
+        const uint64_t base = a.b.hoff[i0], end = (uint64_t)a.b.hoff[last] + a.b.nhits[last];
         const int v = (int)(i / it.nrec);
         const int64_t k = i - (int64_t)v * it.nrec;
-        list_one(a, rec_of(a.rl, it.na, k), v, (size_t)i);
+        if (end - base <= (uint64_t)kListStage) {
+            if (i < it.total) list_one<true>(a, rec_of(a.rl, it.na, k), v, (size_t)i, s_key[wave], s_rec[wave], base);
+            __builtin_amdgcn_wave_barrier();
+            for (uint64_t e = lane; e < end - base; e += 64) {
+                const uint64_t o = base + e;
+                if (o >= cap) break;
+                const uint32_t key = s_key[wave][e];
+                a.b.keys[0][o] = key;
+                a.b.vals[0][o] = (uint32_t)o;
+                a.b.recs[0][o] = s_rec[wave][e];
+                if (per_pixel && ((key >> kSizeBits) & 1u) == 0u) {
+                    float4 *ep = (float4 *)(a.b.ep + o * kEpStride);
+                    ep[0] = ep[1] = ep[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else if (i < it.total) {
+            list_one<false>(a, rec_of(a.rl, it.na, k), v, (size_t)i, nullptr, nullptr, 0);
+        }
     }
 }
 
