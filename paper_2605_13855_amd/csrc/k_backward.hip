@@ -179,7 +179,8 @@ __global__ __launch_bounds__(256) void k_chunk_map(Buffers b)
     for (uint32_t c = b.chunk_off[t]; c < c1; ++c) b.chunk_tile[c] = (uint32_t)t;
 }
 
-// Per-lane sums of the backward over the pixels of its tile entry.
+// Per-lane sums of the backward over the pixels of its tile entry.  g_c* hold
+// sum A_ch alpha; dL/dc_ch = w times that (w is the lane's), taken once at the end.
 struct BwdSums {
     float g_cr, g_cg, g_cb, g_w;
     // moments of dL/de (without the ln 2 of d alpha / de) over the pixel offsets
@@ -215,10 +216,9 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, i
                 const float al = CAP ? fminf(ex, kAlphaMax) : ex;
                 // A . c - s1 (pc.w holds -s1)
                 const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
-                const float aw = al * w;
-                o.g_cr = fmaf(pc.x, aw, o.g_cr);
-                o.g_cg = fmaf(pc.y, aw, o.g_cg);
-                o.g_cb = fmaf(pc.z, aw, o.g_cb);
+                o.g_cr = fmaf(pc.x, al, o.g_cr);
+                o.g_cg = fmaf(pc.y, al, o.g_cg);
+                o.g_cb = fmaf(pc.z, al, o.g_cb);
                 o.g_w = fmaf(al, diff, o.g_w);
                 // dL/de / ln 2 = alpha (B / (1 - alpha) + w diff); zero where alpha is capped
                 const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
@@ -247,12 +247,12 @@ constexpr int kBoxPerGroup = 21;
 // The entry's 10 screen-space partials from the lane's sums:
 // de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
 // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy); the ln 2 of d alpha / de.
-__device__ __forceinline__ void write_partials(float *dst, float qa, float qb, float qc, const BwdSums &o)
+__device__ __forceinline__ void write_partials(float *dst, float qa, float qb, float qc, float w, const BwdSums &o)
 {
     ((float4 *)dst)[0] = make_float4(-(2.f * qa * o.m_x + qb * o.m_y) * kLn2, -(qb * o.m_x + 2.f * qc * o.m_y) * kLn2,
                                      o.m_xx * kLn2, o.m_xy * kLn2);
-    ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, o.g_cr, o.g_cg);
-    ((float2 *)dst)[4] = make_float2(o.g_cb, o.g_w);
+    ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, w * o.g_cr, w * o.g_cg);
+    ((float2 *)dst)[4] = make_float2(w * o.g_cb, o.g_w);
 }
 
 template <int S>
@@ -367,10 +367,9 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
                         const float ex = __builtin_amdgcn_exp2f(e);
                         const float al = may_cap ? fminf(ex, kAlphaMax) : ex;
                         const float diff = fmaf(pc.x, cr, fmaf(pc.y, cg, fmaf(pc.z, cb, pc.w)));
-                        const float aw = al * w;
-                        o.g_cr = fmaf(pc.x, aw, o.g_cr);
-                        o.g_cg = fmaf(pc.y, aw, o.g_cg);
-                        o.g_cb = fmaf(pc.z, aw, o.g_cb);
+                        o.g_cr = fmaf(pc.x, al, o.g_cr);
+                        o.g_cg = fmaf(pc.y, al, o.g_cg);
+                        o.g_cb = fmaf(pc.z, al, o.g_cb);
                         o.g_w = fmaf(al, diff, o.g_w);
                         const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
                         const float dLde = (al < kAlphaMax ? al : 0.f) * dLda;
@@ -384,7 +383,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
                     }
                 }
             }
-            if (valid) write_partials(dst, qa, qb, qc, o);
+            if (valid) write_partials(dst, qa, qb, qc, w, o);
             return;
         }
     }
@@ -427,7 +426,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         if (gn < 0) break;
         g = gn;
     }
-    if (valid) write_partials(dst, qa, qb, qc, o);
+    if (valid) write_partials(dst, qa, qb, qc, w, o);
 }
 
 template <int S>

@@ -271,11 +271,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
     const int tid = threadIdx.x;
     const int seg = (T + kScanThreads - 1) / kScanThreads;
     const int t0 = min(tid * seg, T), t1 = min(t0 + seg, T);
+    // a thread's counts are loaded all at once when they fit in registers (one memory
+    // latency for the segment instead of one per tile)
+    constexpr int kRegs = 32;
+    const bool in_regs = seg <= kRegs;
+    uint32_t ra[kRegs], rd[kRegs];
     unsigned long long se = 0, sc = 0;
-    for (int t = t0; t < t1; ++t) {
-        const uint32_t na = b.cnt_a[t];
-        se += na + b.cnt_d[t];
-        sc += (na + kBwdLanes - 1) / kBwdLanes;
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const bool ok = t0 + j < t1;
+            ra[j] = ok ? b.cnt_a[t0 + j] : 0u;
+            rd[j] = ok ? b.cnt_d[t0 + j] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            se += ra[j] + rd[j];
+            sc += (ra[j] + kBwdLanes - 1) / kBwdLanes;
+        }
+    } else {
+        for (int t = t0; t < t1; ++t) {
+            const uint32_t na = b.cnt_a[t];
+            se += na + b.cnt_d[t];
+            sc += (na + kBwdLanes - 1) / kBwdLanes;
+        }
     }
     s_e[tid] = se;
     s_c[tid] = sc;
@@ -291,12 +310,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
     }
     unsigned long long pe = s_e[tid] - se, pc = s_c[tid] - sc;
     const unsigned long long cap = (unsigned long long)b.pair_cap;
-    for (int t = t0; t < t1; ++t) {
-        b.tile_off[t] = (uint32_t)(pe < cap ? pe : cap);
-        b.chunk_off[t] = (uint32_t)pc;
-        const uint32_t na = b.cnt_a[t];
-        pe += na + b.cnt_d[t];
-        pc += (na + kBwdLanes - 1) / kBwdLanes;
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            if (t0 + j < t1) {
+                b.tile_off[t0 + j] = (uint32_t)(pe < cap ? pe : cap);
+                b.chunk_off[t0 + j] = (uint32_t)pc;
+            }
+            pe += ra[j] + rd[j];
+            pc += (ra[j] + kBwdLanes - 1) / kBwdLanes;
+        }
+    } else {
+        for (int t = t0; t < t1; ++t) {
+            b.tile_off[t] = (uint32_t)(pe < cap ? pe : cap);
+            b.chunk_off[t] = (uint32_t)pc;
+            const uint32_t na = b.cnt_a[t];
+            pe += na + b.cnt_d[t];
+            pc += (na + kBwdLanes - 1) / kBwdLanes;
+        }
     }
     if (tid == kScanThreads - 1) {
         const unsigned long long te = s_e[tid], tc = s_c[tid];
