@@ -190,6 +190,34 @@ def test_l1_loss_matches_oracle():
     np.testing.assert_array_equal(to_np(gi).reshape(3, 128, 128), g.astype(np.float32).astype(np.float64))
 
 
+def test_odd_pixel_counts_take_the_scalar_pixel_kernels():
+    """A batch whose first view has an odd pixel count (101 x 77), so that the second
+    view's planes start off any 16-byte boundary: L1 loss and gradient, images and
+    parameter gradients against the oracle."""
+    sc = scenes.random_scene(26, 1500, 64, 48, n_views=1, mean_range=1.0)
+    sc.cameras = [scenes.orbit_camera(3.5, 0.2, 0.0, 101, 77), scenes.orbit_camera(3.5, -0.3, 0.1, 64, 48)]
+    rng = np.random.default_rng(26)
+    sc.targets = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cameras]
+    dense_case(sc, 16, 64)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n)
+    r.fit_pair_capacity(params, sigma, sc.background)
+    r.forward(params, sigma, sc.background)
+    tgt = r.pack(sc.targets)
+    gi = torch.zeros_like(r.image)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    oit.l1_loss(r.image, tgt, r.cams_arr, r.n_views, gi, loss, r.ws)
+    torch.cuda.synchronize()
+    L_tot = 0.0
+    for k, cam in enumerate(sc.cameras):
+        img = to_np(r.views(r.image, 3)[k])
+        L, g = O.l1_loss(img, sc.targets[k])
+        L_tot += L
+        np.testing.assert_array_equal(to_np(r.views(gi, 3)[k]), g.astype(np.float32).astype(np.float64))
+    assert float(loss.item()) == pytest.approx(L_tot, rel=1e-7)
+
+
 # ---------------------------------------------------------------------------------
 # active set
 # ---------------------------------------------------------------------------------
