@@ -651,20 +651,35 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
         const size_t pv = (size_t)v * nrec + t;
         const uint64_t cap = (uint64_t)a.b.pair_cap;
         const uint64_t g0 = a.b.hoff[pv], nh = a.b.nhits[pv];
-        for (uint64_t k = 0; k < nh && g0 + k < cap; ++k) {
-            const float *e = a.b.ep + (g0 + k) * kEpStride;
-            const float4 e0 = ((const float4 *)e)[0], e1 = ((const float4 *)e)[1];
-            const float2 e2 = ((const float2 *)e)[4];
-            gs[0] += e0.x;
-            gs[1] += e0.y;
-            gs[2] += e0.z;
-            gs[3] += e0.w;
-            gs[4] += e1.x;
-            gs[5] += e1.y;
-            gs[6] += e1.z;
-            gs[7] += e1.w;
-            gs[8] += e2.x;
-            gs[9] += e2.y;
+        const uint64_t n = g0 >= cap ? 0 : (nh < cap - g0 ? nh : cap - g0);
+        // rows four at a time: the loads are issued together, the sums stay in row order
+        for (uint64_t k = 0; k < n; k += 4) {
+            float4 e0[4], e1[4];
+            float2 e2[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (k + j < n) {
+                    const float *e = a.b.ep + (g0 + k + j) * kEpStride;
+                    e0[j] = ((const float4 *)e)[0];
+                    e1[j] = ((const float4 *)e)[1];
+                    e2[j] = ((const float2 *)e)[4];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (k + j < n) {
+                    gs[0] += e0[j].x;
+                    gs[1] += e0[j].y;
+                    gs[2] += e0[j].z;
+                    gs[3] += e0[j].w;
+                    gs[4] += e1[j].x;
+                    gs[5] += e1[j].y;
+                    gs[6] += e1[j].z;
+                    gs[7] += e1[j].w;
+                    gs[8] += e2[j].x;
+                    gs[9] += e2[j].y;
+                }
+            }
         }
     }
     bool any = false;
