@@ -895,8 +895,9 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     constexpr int NW = NT / 64;            // waves (= blocks)
     constexpr int RSTEP = 64 / BW;         // rows between one thread's pixels
     static_assert(NW == WPR * WPR && PPT * RSTEP == BW, "wave blocks must tile the tile");
-    __shared__ float4 s_rec[BATCH * 3];
-    __shared__ int s_mask[BATCH];
+    // the active pass stages BATCH records per block; the label-change pass 64 per wave
+    __shared__ float4 s_rec[(BAU ? NW * 64 : BATCH) * 3];
+    __shared__ int s_mask[BAU ? 1 : BATCH];
 
     const int tile = blockIdx.x;
     const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
@@ -947,41 +948,52 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
             Tp[p] = Tm[p] = 1.f;
         }
         int since_fold = 0;
-        for (uint64_t base = 0; base < nd; base += BATCH) {
-            const int cnt = (int)(nd - base < (uint64_t)BATCH ? nd - base : (uint64_t)BATCH);
-            __syncthreads();
-            for (int j = threadIdx.x; j < cnt; j += NT) {
-                const uint32_t ri = a.b.entries[off + na + base + j];
-                const Rec r = (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec;
-                // bit 8: the record leaves the pre-rendered set's complement (sign -1)
-                s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j], r, x0, y0) | (r.c.w < 0.f ? 0x100 : 0);
-            }
-            __syncthreads();
-            for (int sb = 0; sb < cnt; sb += 64) {
-              // the staged records that reach this wave's block, one bit each, by sign
-              const int m = sb + lane < cnt ? s_mask[sb + lane] : 0;
-              const bool mine = (m & wbit) != 0;
-              uint64_t todo_p = __ballot(mine && !(m & 0x100)), todo_m = __ballot(mine && (m & 0x100));
-              // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
-              while (todo_p) {
-                const int j = sb + (int)__builtin_ctzll(todo_p);
+        // Each wave stages the tile's label changes itself, 64 at a time (one per lane),
+        // in its own LDS slice, and keeps those that reach its pixel block: the waves of
+        // a tile never wait for one another, and a wave whose block the changes miss
+        // ends early.
+        // The loads are pipelined: a batch's entry indices are read two batches ahead and
+        // its records one batch ahead, so both latencies overlap the work on a batch.
+        float4 *wrec = s_rec + wave * 64 * 3;
+        const uint32_t *ent = a.b.entries + off + na;
+        auto rec_of_entry = [&](uint32_t ri) { return (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec; };
+        Rec cur = kNoRec;
+        uint32_t ri_next = 0xffffffffu;
+        if (lane < nd) cur = rec_of_entry(ent[lane]);
+        if (64 + lane < nd) ri_next = ent[64 + lane];
+        for (uint64_t base = 0; base < nd; base += 64) {
+            const int cnt = (int)(nd - base < 64 ? nd - base : 64);
+            int m = 0;
+            // bit 8: the record leaves the pre-rendered set's complement (sign -1)
+            if (lane < cnt) m = stage_rec<BW, WPR, NW>(&wrec[3 * lane], cur, x0, y0) | (cur.c.w < 0.f ? 0x100 : 0);
+            __builtin_amdgcn_wave_barrier();
+            // next batch's records (their indices are here), the batch after's indices
+            cur = kNoRec;
+            if (base + 64 + lane < nd) cur = rec_of_entry(ri_next);
+            ri_next = 0xffffffffu;
+            if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
+            const bool mine = (m & wbit) != 0;
+            uint64_t todo_p = __ballot(mine && !(m & 0x100)), todo_m = __ballot(mine && (m & 0x100));
+            // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
+            while (todo_p) {
+                const int j = (int)__builtin_ctzll(todo_p);
                 todo_p &= todo_p - 1;
-                bau_record<PPT>(s_rec + 3 * j, colf, rowf, 1.f, dP0, dP1, dQ0, dQ1, Tp);
+                bau_record<PPT>(wrec + 3 * j, colf, rowf, 1.f, dP0, dP1, dQ0, dQ1, Tp);
                 if (++since_fold == kFold) {
                     since_fold = 0;
                     fold_log_t<PPT>(dL, Tp, Tm);
                 }
-              }
-              while (todo_m) {
-                const int j = sb + (int)__builtin_ctzll(todo_m);
-                todo_m &= todo_m - 1;
-                bau_record<PPT>(s_rec + 3 * j, colf, rowf, -1.f, dP0, dP1, dQ0, dQ1, Tm);
-                if (++since_fold == kFold) {
-                    since_fold = 0;
-                    fold_log_t<PPT>(dL, Tp, Tm);
-                }
-              }
             }
+            while (todo_m) {
+                const int j = (int)__builtin_ctzll(todo_m);
+                todo_m &= todo_m - 1;
+                bau_record<PPT>(wrec + 3 * j, colf, rowf, -1.f, dP0, dP1, dQ0, dQ1, Tm);
+                if (++since_fold == kFold) {
+                    since_fold = 0;
+                    fold_log_t<PPT>(dL, Tp, Tm);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         fold_log_t<PPT>(dL, Tp, Tm);
 #pragma unroll

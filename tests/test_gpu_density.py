@@ -267,3 +267,32 @@ def test_checkpoint_resume_schedule_trainer_bitwise(tmp_path):
     assert torch.equal(a.labels[a.epoch], b.labels[b.epoch])
     for pa, pb in zip(a.pre, b.pre):
         assert torch.equal(pa, pb)
+
+
+def test_checkpoint_resume_active_set_trainer_bitwise(tmp_path):
+    """The top-k-every-step trainer resumed into a captured HIP graph: the state is
+    restored in place, so the graph's replays continue the saved run bit for bit."""
+    from paper_2605_13855_amd.render import ActiveSetTrainer
+    sc = scenes.random_scene(97, 3000, 64, 48, n_views=2, mean_range=1.0)
+
+    def make():
+        t = ActiveSetTrainer(sc, fraction=0.2, tile=16, sigma_lr=0.0)
+        t.warmup_dense_scores()
+        return t
+
+    a = make()
+    for _ in range(3):
+        a.iteration()
+    path = tmp_path / "active.safetensors"
+    checkpoint.save(a, path)
+    for _ in range(4):
+        a.iteration()
+    b = make()
+    b.capture()                      # one eager warm-up iteration, then the graph
+    checkpoint.load(b, path)
+    for _ in range(4):
+        b.replay()
+    torch.cuda.synchronize()
+    eq, what = states_equal(a, b)
+    assert eq, what
+    assert torch.equal(a.label, b.label) and torch.equal(a.pre, b.pre)
