@@ -7,10 +7,9 @@ the densification statistic and its random generator, or the label arrays, the
 per-view pre-rendered buffers and the parameter snapshot), plus JSON metadata for the
 host state (iteration counters, the view order, the numpy generator, pair capacity).
 Loading restores into a trainer built for the same scene; its splat count may differ
-(densification), so the trainer's buffers are rebuilt to the checkpoint's size.  With
-the same kernels, a resumed run repeats the uninterrupted one bit for bit wherever the
-kernels are deterministic (everything but sigma's gradient, whose FP64 block sums are
-added in arrival order).
+(densification), so the trainer's buffers are rebuilt to the checkpoint's size.  The
+kernels are deterministic (no order-dependent sums), so a resumed run repeats the
+uninterrupted one bit for bit.
 """
 from __future__ import annotations
 

@@ -23,6 +23,35 @@ __device__ __forceinline__ void block_add_double(double v, double *dst)
     }
 }
 
+// The block's sum of v, on thread 0 (fixed order: lanes by a butterfly, waves in turn).
+__device__ __forceinline__ double block_sum_double(double v)
+{
+    __shared__ double s_sum[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s_sum[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) t += s_sum[w];
+    }
+    return t;
+}
+
+// dL/dsigma: the per-block shares of the pixel constants' pass (inactive set) and of the
+// preprocess backward, added in block order by one wave, so that the result does not
+// depend on the order in which blocks finish.
+__global__ void k_sigma_total(const double *part, int npix, int npre, double *grad_sigma)
+{
+    const int lane = threadIdx.x;
+    double t = 0.0;
+    for (int i = lane; i < npix; i += 64) t += part[i];
+    for (int i = lane; i < npre; i += 64) t += part[kSigPixParts + i];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) *grad_sigma = t;
+}
+
 __device__ __forceinline__ int view_of_pixel(const CamDev *cams, int n_views, int64_t gp)
 {
     int v = 0;
@@ -44,7 +73,7 @@ struct LossArgs {
 // Grid of the per-pixel kernels: a grid-stride loop over the batch's pixels with at most
 // kPixBlocks blocks, so that the one FP64 atomic per block onto a single address stays
 // a few thousand operations instead of one per 256 pixels.
-constexpr int64_t kPixBlocks = 2048;
+constexpr int64_t kPixBlocks = kSigPixParts;
 
 static unsigned pixel_blocks(int64_t total_px)
 {
@@ -130,9 +159,10 @@ __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
                    (double)A2 * ((double)pr[5 * HW] - (double)F[2] * Q1);
         }
     }
-    if (a.pre) {
+    const double t = block_sum_double(acc);
+    if (threadIdx.x == 0) {
         const double sig = (double)*a.sigma;
-        block_add_double(acc / (sig * sig), a.grad_sigma);
+        a.b.sig_part[blockIdx.x] = a.pre ? t / (sig * sig) : 0.0;
     }
 }
 
@@ -807,7 +837,7 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
 // the 64 SH outputs.  Also the activeness score (Sec. 4.1) and dL/dsigma (FP64).
 // ---------------------------------------------------------------------------------
 constexpr int kPbThreads = 256;
-constexpr unsigned kPbBlocks = 1024;
+constexpr unsigned kPbBlocks = kSigPreParts;
 
 __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
 {
@@ -967,7 +997,8 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
         }
         __syncthreads();
     }
-    block_add_double(gsig, a.grad_sigma);
+    const double t = block_sum_double(gsig);
+    if (threadIdx.x == 0) a.b.sig_part[kSigPixParts + blockIdx.x] = t;
 }
 
 void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowList &rl, const Buffers &b,
@@ -990,6 +1021,8 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
     int64_t blocks = (rl.Acap + rows_per_block - 1) / rows_per_block;
     if (blocks > kPbBlocks) blocks = kPbBlocks;
     if (blocks > 0) hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)blocks), dim3(kPbThreads), 0, s, a);
+    hipLaunchKernelGGL(k_sigma_total, dim3(1), dim3(64), 0, s, (const double *)b.sig_part,
+                       (int)pixel_blocks(b.total_px), (int)blocks, grad_sigma);
 }
 
 }  // namespace oit

@@ -62,7 +62,8 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
     size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, orig, keys0, keys1, vals0,
-        vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, total;
+        vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, sig_part,
+        total;
     uint32_t max_chunks;
     int T;
     int64_t total_px, Acap, Rcap;
@@ -186,6 +187,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.ep = o; o = align256(o + 4 * kEpStride * pc);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
+    p.sig_part = o; o = align256(o + 8 * (size_t)(kSigPixParts + kSigPreParts));
     p.total = o;
     return OIT_OK;
 }
@@ -221,6 +223,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.ep = (float *)(w + p.ep);
     b.pixconst = (float4 *)(w + p.pixconst);
     b.pixB = (float *)(w + p.pixB);
+    b.sig_part = (double *)(w + p.sig_part);
     b.n_views = n_views;
     b.T = p.T;
     b.tile = tu->tile;
@@ -471,7 +474,6 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
     fill_u32(b.counters + CNT_BOX_ITEMS, 1, 0u, s);
-    fill_f64(grad_sigma, 1, 0.0, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
     const KTimer bwd_t{g_ev[4], g_ev[5]};
     if (!launch_raster_bwd(b, rl, s, g_timing_on ? &bwd_t : nullptr))

@@ -18,6 +18,8 @@ constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (e
 constexpr int kRadixBits = 5;                  // digit width of a radix-sort pass
 constexpr int kRadixBuckets = 1 << kRadixBits;
 constexpr int kSizeBits = 5;                   // footprint-size class below (tile, class) in the sort key
+constexpr int kSigPixParts = 2048;             // blocks of the per-pixel backward kernels (at most)
+constexpr int kSigPreParts = 1024;             // blocks of the preprocess backward (at most)
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
@@ -75,6 +77,7 @@ struct Buffers {
     float *ep;                                  // [pair_cap][kEpStride] screen-space partials, by unsorted slot
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
     float *pixB;                                // [total_px] B
+    double *sig_part;                           // [kSigPixParts + kSigPreParts] per-block shares of dL/dsigma
     uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
     int64_t total_px, pair_cap;

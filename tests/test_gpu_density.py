@@ -218,11 +218,11 @@ def states_equal(a, b):
 
 def test_checkpoint_resume_densifying_trainer_bitwise(tmp_path):
     """Save in the middle of a densification interval, resume in a trainer built with
-    another seed: the next iterations (a densification among them) repeat bit for bit.
-    sigma is held fixed (its gradient's FP64 block sums are added in arrival order)."""
+    another seed: the next iterations (a densification and an opacity reset among them)
+    repeat bit for bit, sigma included."""
     sc = small_training_scene()
     kw = dict(densify_from=0, densify_until=100, densify_interval=5, opacity_reset_interval=7,
-              grad_threshold=2e-5, keep_probability=0.6, sigma_lr=0.0, loss="l1")
+              grad_threshold=2e-5, keep_probability=0.6, loss="l1")
     a = DensifyingTrainer(sc, seed=5, **kw)
     for _ in range(3):
         a.iteration()
@@ -248,7 +248,7 @@ def test_checkpoint_resume_schedule_trainer_bitwise(tmp_path):
     probe.update_active_set()
     eps = [float(np.quantile(to_np(probe.score), 0.7))] * 6
     del probe
-    kw = dict(interval=4, n_sub=2, lr=5e-3, sigma_lr=0.0, loss="l1")
+    kw = dict(interval=4, n_sub=2, lr=5e-3, loss="l1")
     a = PaperScheduleTrainer(sc, eps=eps, seed=2, **kw)
     for _ in range(6):
         a.iteration()
@@ -276,7 +276,7 @@ def test_checkpoint_resume_active_set_trainer_bitwise(tmp_path):
     sc = scenes.random_scene(97, 3000, 64, 48, n_views=2, mean_range=1.0)
 
     def make():
-        t = ActiveSetTrainer(sc, fraction=0.2, tile=16, sigma_lr=0.0)
+        t = ActiveSetTrainer(sc, fraction=0.2, tile=16)
         t.warmup_dense_scores()
         return t
 
