@@ -187,9 +187,11 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // entry's own row at its unsorted slot (no atomics: a (record, view) pair's slots are
 // contiguous, and the preprocess backward sums them in a fixed order).
 //
-// The work items are split into 8 contiguous ranges, one per XCD, so that the waves
-// that share a tile's pixel constants share an L2; a wave whose range is drained
-// moves on to the next range.
+// Work items go to the XCDs in blocks of 64 consecutive items (block b to XCD b mod 8),
+// so that each XCD gets a mix of the batch and the waves working on one tile share an
+// L2.  The waves of an XCD take its items in order from the XCD's own queue, one device
+// ticket per item; a wave stops when its queue is drained.  Same-address device atomics
+// serialise at the memory side, so no wave polls the other XCDs' queues.
 //
 // Screen-space gradient layout (10 floats): d/dmx, d/dmy, d/dqa, d/dqb, d/dqc, d/dlo,
 // d/dc (rgb), d/dw -- q* and lo as in the record.
@@ -286,8 +288,9 @@ __device__ __forceinline__ void write_partials(float *dst, float qa, float qb, f
 }
 
 template <int S>
+// boxed: the wave's count of items walked box by box (for the counters)
 __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
-                                         float4 (*s_c)[64], float (*s_B)[64])
+                                         float4 (*s_c)[64], float (*s_B)[64], uint32_t &boxed)
 {
     constexpr int GX = S / kGroup;   // groups per tile edge
     const uint64_t cap = (uint64_t)b.pair_cap;
@@ -368,7 +371,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         int amax = area;
         for (int m = 32; m > 0; m >>= 1) amax = max(amax, __shfl_xor(amax, m));
         if (amax <= kBoxPerGroup * __builtin_popcount(mask)) {
-            if (lane == 0) atomicAdd(&b.counters[CNT_BOX_ITEMS], 1u);
+            ++boxed;
             BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             int c = bc0, r = br0;
             // the constants of the lane's next box pixel are fetched one pixel ahead
@@ -468,17 +471,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
     if (total > a.b.max_chunks) total = a.b.max_chunks;
     const int xcd = (int)(blockIdx.x % kXcds);
-    for (int k = 0; k < kXcds; ++k) {
-        const int q = (xcd + k) % kXcds;
-        const uint32_t q0 = (uint32_t)(((uint64_t)total * q) / kXcds);
-        const uint32_t q1 = (uint32_t)(((uint64_t)total * (q + 1)) / kXcds);
-        for (;;) {
-            uint32_t ticket = 0;
-            if (lane == 0) ticket = atomicAdd(&a.b.counters[CNT_XQUEUE + q], 1u);
-            ticket = __builtin_amdgcn_readfirstlane(ticket);
-            if (ticket >= q1 - q0) break;
-            bwd_item<S>(a.b, q0 + ticket, wave, lane, s_c, s_B);
-        }
+    uint32_t boxed = 0;
+    for (;;) {
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(&a.b.counters[CNT_XQUEUE + xcd], 1u);
+        ticket = __builtin_amdgcn_readfirstlane(ticket);
+        // the ticket-th item of this XCD: block xcd + 8 (ticket / 64), offset ticket % 64
+        const uint64_t item = ((uint64_t)xcd + (uint64_t)kXcds * (ticket >> 6)) * 64 + (ticket & 63u);
+        if (item >= total) break;   // items grow with the ticket: the queue is drained
+        bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, boxed);
+    }
+    // one atomic per block for the box-walk counter
+    __shared__ uint32_t s_boxed[4];
+    if (lane == 0) s_boxed[wave] = boxed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t n = s_boxed[0] + s_boxed[1] + s_boxed[2] + s_boxed[3];
+        if (n) atomicAdd(&a.b.counters[CNT_BOX_ITEMS], n);
     }
 }
 
@@ -581,8 +590,9 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
 }
 
 // Persistent grid of the per-splat backward: 8 workgroups of 4 waves per CU of the
-// largest device (256 CUs); surplus workgroups find the queues drained and exit.
+// largest device (256 CUs); a multiple of the 8 XCDs, so that every XCD's queue is served.
 constexpr unsigned kBwdBlocks = 2048;
+static_assert(kBwdBlocks % kXcds == 0, "every XCD queue needs workgroups");
 
 template <int S>
 static void launch_bwd_pixel_s(const BwdArgs &a, dim3 block, hipStream_t s, const KTimer *t)

@@ -1048,8 +1048,9 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
             unsigned long long t = 0;
             for (int w = 0; w < (NT + 63) / 64; ++w) t += s_cnt[w];
             const int inside = min(S, cam.W - tx * S) * min(S, cam.H - ty * S);
-            if (t) atomicAdd((unsigned long long *)(a.b.counters + CNT_PAIRS), t);
-            if (na) atomicAdd((unsigned long long *)(a.b.counters + CNT_EVAL), (unsigned long long)na * inside);
+            // the tile's counts; k_pair_totals adds them (no device atomics per tile)
+            a.b.tile_cnt[2 * (size_t)tile] = t;
+            a.b.tile_cnt[2 * (size_t)tile + 1] = (unsigned long long)na * inside;
         }
     }
 
@@ -1109,11 +1110,38 @@ static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTime
     }
 }
 
+// Throughput counters of the active pass: the per-tile counts summed by one block.
+__global__ __launch_bounds__(1024) void k_pair_totals(Buffers b)
+{
+    __shared__ unsigned long long s_p[1024], s_e[1024];
+    unsigned long long p = 0, e = 0;
+    for (int t = threadIdx.x; t < b.T; t += 1024) {
+        p += b.tile_cnt[2 * (size_t)t];
+        e += b.tile_cnt[2 * (size_t)t + 1];
+    }
+    s_p[threadIdx.x] = p;
+    s_e[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s_p[threadIdx.x] += s_p[threadIdx.x + off];
+            s_e[threadIdx.x] += s_e[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *(unsigned long long *)(b.counters + CNT_PAIRS) = s_p[0];
+        *(unsigned long long *)(b.counters + CNT_EVAL) = s_e[0];
+    }
+}
+
 template <int S>
 static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s, const KTimer *bau_t, const KTimer *fwd_t)
 {
     if (a.pre && !raster_fwd_s<S, true>(a, batch, s, bau_t)) return false;
-    return raster_fwd_s<S, false>(a, batch, s, fwd_t);
+    if (!raster_fwd_s<S, false>(a, batch, s, fwd_t)) return false;
+    hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(1024), 0, s, a.b);
+    return true;
 }
 
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,

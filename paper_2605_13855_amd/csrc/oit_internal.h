@@ -23,9 +23,9 @@ constexpr int kSigPreParts = 1024;             // blocks of the preprocess backw
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
-// CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue counters
 // CNT_NPAIRS: (listed record, view) pairs of the call; CNT_SORT_N: tile entries that fit
 // the pair capacity (the sorted list's length)
+// CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue tickets
 // CNT_BOX_ITEMS: backward work items that took the footprint-box walk
 enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
        CNT_BOX_ITEMS = 16, CNT_SLOTS = 32 };
@@ -78,6 +78,7 @@ struct Buffers {
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
     float *pixB;                                // [total_px] B
     double *sig_part;                           // [kSigPixParts + kSigPreParts] per-block shares of dL/dsigma
+    unsigned long long *tile_cnt;               // [T][2] contributing / evaluated active pairs per tile
     uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
     int64_t total_px, pair_cap;
