@@ -74,47 +74,52 @@ def test_split_children_lie_on_the_rotated_axes():
 
 
 def hand_set():
-    """Eight splats, one per case (statistic = accum / denom, extent 10 => clone when
-    max scale <= 0.1):
+    """Eleven splats, one per case (statistic = accum / denom, extent 10 => clone when
+    max scale <= 0.1; world limit 0.5 x 10 = 5; screen limit 20 px):
       0 not a candidate, kept            1 candidate, small, drawn in -> cloned
       2 candidate, large -> split        3 opacity below the minimum -> pruned
       4 candidate, small, low opacity -> original and copy pruned
       5 candidate, large -> split        6 original too large on screen -> pruned
-      7 candidate by gradient, drawn out (u >= p) -> kept as it is"""
-    p = splats(8)
-    for i in range(8):
+      7 candidate by gradient, drawn out (u >= p) -> kept as it is
+      8 candidate, small, too large on screen -> original pruned, its copy kept
+      9 sum above the threshold, mean (sum / 3 views) below -> kept as it is
+     10 candidate with largest scale 6 > 5 -> split; children (6 / 1.6) kept"""
+    p = splats(11)
+    for i in range(11):
         set_splat(p, i, (0.1 * i, 0.0, 0.0), 0.05, logit=0.0)
     for i in (2, 5):
         p["log_scale"][:, i] = np.log([0.3, 0.1, 0.1])
+    p["log_scale"][:, 10] = np.log([6.0, 0.1, 0.1])
     p["opacity_logit"][0, 3] = -7.0
     p["opacity_logit"][0, 4] = -7.0
-    accum = np.array([1e-4, 5e-3, 6e-3, 0, 4e-3, 2e-3, 0, 9e-3])
-    denom = np.array([1, 2, 2, 1, 1, 1, 1, 3], float)
-    radius = np.array([5, 5, 5, 5, 5, 5, 25, 5], float)
-    uniform = np.array([0.9, 0.3, 0.1, 0.2, 0.4, 0.49, 0.1, 0.7])
+    accum = np.array([1e-4, 5e-3, 6e-3, 0, 4e-3, 2e-3, 0, 9e-3, 4e-3, 2.4e-3, 2e-3])
+    denom = np.array([1, 2, 2, 1, 1, 1, 1, 3, 1, 3, 1], float)
+    radius = np.array([5, 5, 5, 5, 5, 5, 25, 5, 25, 5, 5], float)
+    uniform = np.array([0.9, 0.3, 0.1, 0.2, 0.4, 0.49, 0.1, 0.7, 0.3, 0.1, 0.2])
     return p, accum, denom, radius, uniform
 
 
 def test_densify_hand_case_order_and_moments():
     p, accum, denom, radius, uniform = hand_set()
     rng = np.random.default_rng(7)
-    m = {g: rng.normal(size=(c, 8)) for g, c in O.GROUPS}
-    v = {g: rng.random(size=(c, 8)) for g, c in O.GROUPS}
-    normals = rng.normal(size=(8, 2, 3))
+    m = {g: rng.normal(size=(c, 11)) for g, c in O.GROUPS}
+    v = {g: rng.random(size=(c, 11)) for g, c in O.GROUPS}
+    normals = rng.normal(size=(11, 2, 3))
     q, qm, qv, src = O.densify(p, m, v, accum, denom, radius, uniform, normals, RULES)
-    # originals 0, 1, 7; clone of 1; first children of 2, 5; second children of 2, 5
-    np.testing.assert_array_equal(src, [0, 1, 7, 1, 2, 5, 2, 5])
-    for j, i in enumerate([0, 1, 7]):
+    # originals 0, 1, 7, 9; clones of 1, 8; first children of 2, 5, 10; second children
+    np.testing.assert_array_equal(src, [0, 1, 7, 9, 1, 8, 2, 5, 10, 2, 5, 10])
+    for j, i in enumerate([0, 1, 7, 9]):
         for g, _ in O.GROUPS:
             np.testing.assert_array_equal(q[g][:, j], p[g][:, i])
             np.testing.assert_array_equal(qm[g][:, j], m[g][:, i])
             np.testing.assert_array_equal(qv[g][:, j], v[g][:, i])
-    for j in range(3, 8):
+    for j in range(4, 12):
         for g, _ in O.GROUPS:
             assert not qm[g][:, j].any() and not qv[g][:, j].any()
     for g, _ in O.GROUPS:
-        np.testing.assert_array_equal(q[g][:, 3], p[g][:, 1])
-    for j, (i, k) in zip(range(4, 8), [(2, 0), (5, 0), (2, 1), (5, 1)]):
+        np.testing.assert_array_equal(q[g][:, 4], p[g][:, 1])
+        np.testing.assert_array_equal(q[g][:, 5], p[g][:, 8])
+    for j, (i, k) in zip(range(6, 12), [(2, 0), (5, 0), (10, 0), (2, 1), (5, 1), (10, 1)]):
         ch = O.split_child(p, i, normals[i][k])
         for g, _ in O.GROUPS:
             np.testing.assert_array_equal(q[g][:, j], ch[g])
@@ -122,10 +127,11 @@ def test_densify_hand_case_order_and_moments():
 
 def test_keep_probability_extremes_and_count():
     p, accum, denom, radius, uniform = hand_set()
-    zeros = {g: np.zeros((c, 8)) for g, c in O.GROUPS}
-    normals = np.zeros((8, 2, 3))
-    # p = 0: nothing densifies; p = 1: 7 (mean 3e-3, small) is cloned as well
-    for prob, want in ((0.0, [0, 1, 2, 5, 7]), (1.0, [0, 1, 7, 1, 7, 2, 5, 2, 5])):
+    zeros = {g: np.zeros((c, 11)) for g, c in O.GROUPS}
+    normals = np.zeros((11, 2, 3))
+    # p = 0: nothing densifies (10 is then an original beyond the world limit: pruned);
+    # p = 1: 7 (mean 3e-3, small) is cloned as well
+    for prob, want in ((0.0, [0, 1, 2, 5, 7, 9]), (1.0, [0, 1, 7, 9, 1, 7, 8, 2, 5, 10, 2, 5, 10])):
         r = O.DensityRules(**{**RULES.__dict__, "keep_probability": prob})
         _, _, _, src = O.densify(p, zeros, zeros, accum, denom, radius, uniform, normals, r)
         np.testing.assert_array_equal(src, want)
