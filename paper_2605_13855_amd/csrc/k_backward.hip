@@ -187,9 +187,9 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // entry's own row at its unsorted slot (no atomics: a (record, view) pair's slots are
 // contiguous, and the preprocess backward sums them in a fixed order).
 //
-// Work items go to the XCDs in blocks of 64 consecutive items (block b to XCD b mod 8),
-// so that each XCD gets a mix of the batch and the waves working on one tile share an
-// L2.  The waves of an XCD take its items in order from the XCD's own queue, one device
+// Work items go to the XCDs in blocks of consecutive items (block b to XCD b mod 8), so
+// that each XCD gets a mix of the batch and the waves working on one tile share an L2;
+// a block holds about ten tiles' items (64 items when tiles have few, up to 1024).  The waves of an XCD take its items in order from the XCD's own queue, one device
 // ticket per item; a wave stops when its queue is drained.  Same-address device atomics
 // serialise at the memory side, so no wave polls the other XCDs' queues.
 //
@@ -471,13 +471,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
     if (total > a.b.max_chunks) total = a.b.max_chunks;
     const int xcd = (int)(blockIdx.x % kXcds);
+    // block size: 64 items per six items of the average tile, a power of two up to 1024
+    const uint32_t per_tile = total / (uint32_t)(a.b.T > 0 ? a.b.T : 1);
+    const uint32_t want = 64u * ((per_tile + 5u) / 6u);
+    int lb = 6;
+    while ((1u << lb) < want && lb < 10) ++lb;
     uint32_t boxed = 0;
     for (;;) {
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(&a.b.counters[CNT_XQUEUE + xcd], 1u);
         ticket = __builtin_amdgcn_readfirstlane(ticket);
-        // the ticket-th item of this XCD: block xcd + 8 (ticket / 64), offset ticket % 64
-        const uint64_t item = ((uint64_t)xcd + (uint64_t)kXcds * (ticket >> 6)) * 64 + (ticket & 63u);
+        // the ticket-th item of this XCD: block xcd + 8 (ticket / B), offset ticket % B
+        const uint64_t item = (((uint64_t)xcd + (uint64_t)kXcds * (ticket >> lb)) << lb) + (ticket & ((1u << lb) - 1u));
         if (item >= total) break;   // items grow with the ticket: the queue is drained
         bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, boxed);
     }
