@@ -52,12 +52,22 @@ __global__ void k_sigma_total(const double *part, int npix, int npre, double *gr
     if (lane == 0) *grad_sigma = t;
 }
 
-__device__ __forceinline__ int view_of_pixel(const CamDev *cams, int n_views, int64_t gp)
+// The pixels gp = tid, tid + stride, ... of the batch, as a flat grid-stride loop visits
+// them and in the same order, but taken view by view so that the view's pixel base and
+// size are wave-uniform: f(pix_base, HW, local) with gp = pix_base + local.  The views'
+// pixels are contiguous and their total fits an int (the plan checks 9 x pixels).
+template <class F>
+__device__ __forceinline__ void for_batch_pixels(const Buffers &b, F &&f)
 {
-    int v = 0;
-    for (int k = 1; k < n_views; ++k)
-        if (gp >= cams[k].pix_base) v = k;
-    return v;
+    const int stride = (int)(gridDim.x * blockDim.x);
+    const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    for (int v = 0; v < b.n_views; ++v) {
+        const int pb = b.cams[v].pix_base;
+        const int hw = b.cams[v].W * b.cams[v].H;
+        int local = tid - pb;
+        if (local < 0) local += ((stride - 1 - local) / stride) * stride;
+        for (; local < hw; local += stride) f((size_t)pb, (size_t)hw, (size_t)local);
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -84,22 +94,20 @@ static unsigned pixel_blocks(int64_t total_px)
 __global__ __launch_bounds__(256) void k_l1_loss(LossArgs a)
 {
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < a.b.total_px; gp += stride) {
-        const int v = view_of_pixel(a.b.cams, a.b.n_views, gp);
-        const CamDev &cam = a.b.cams[v];
-        const size_t HW = (size_t)cam.W * cam.H;
-        const size_t local = (size_t)(gp - cam.pix_base);
-        const size_t base = 3 * (size_t)cam.pix_base + local;
+    const float *__restrict__ image = a.image;
+    const float *__restrict__ target = a.target;
+    float *__restrict__ grad = a.grad;
+    for_batch_pixels(a.b, [&](size_t pb, size_t HW, size_t local) {
+        const size_t base = 3 * pb + local;
         const float inv = 1.f / (3.f * (float)HW);
         const double dinv = 1.0 / (3.0 * (double)HW);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const float d = a.image[base + ch * HW] - a.target[base + ch * HW];
-            a.grad[base + ch * HW] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+            const float d = image[base + ch * HW] - target[base + ch * HW];
+            grad[base + ch * HW] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
             acc += fabs((double)d) * dinv;
         }
-    }
+    });
     block_add_double(acc, a.loss);
 }
 
@@ -129,40 +137,47 @@ struct PixArgs {
     double *grad_sigma;
 };
 
+// PRE: a pre-rendered inactive set is given (its loads are issued with the others).
+template <bool PRE>
 __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
 {
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gp < a.b.total_px; gp += stride) {
-        const int v = view_of_pixel(a.b.cams, a.b.n_views, gp);
-        const CamDev &cam = a.b.cams[v];
-        const size_t HW = (size_t)cam.W * cam.H;
-        const size_t local = (size_t)(gp - cam.pix_base);
-        const size_t pb = (size_t)cam.pix_base;
-        const float *ps = a.pixstate + 5 * pb + local;
-        const float *gr = a.grad + 3 * pb + local;
+    const float *__restrict__ pixstate = a.pixstate;
+    const float *__restrict__ grad = a.grad;
+    const float *__restrict__ pre = a.pre;
+    float4 *__restrict__ pixconst = a.b.pixconst;
+    float *__restrict__ pixB = a.b.pixB;
+    for_batch_pixels(a.b, [&](size_t pb, size_t HW, size_t local) {
+        const float *ps = pixstate + 5 * pb + local;
+        const float *gr = grad + 3 * pb + local;
         const float T = ps[0], Q = ps[HW];
         const float F[3] = {ps[2 * HW], ps[3 * HW], ps[4 * HW]};
         const float g[3] = {gr[0], gr[HW], gr[2 * HW]};
+        float P1[3] = {0.f, 0.f, 0.f}, Q1 = 0.f;
+        if constexpr (PRE) {
+            const float *pr = pre + 9 * pb + local;
+            P1[0] = pr[3 * HW];
+            P1[1] = pr[4 * HW];
+            P1[2] = pr[5 * HW];
+            Q1 = pr[7 * HW];
+        }
         const float k = Q > 0.f ? (1.f - T) / Q : 0.f;
         const float A0 = g[0] * k, A1 = g[1] * k, A2 = g[2] * k;
         const float s1 = A0 * F[0] + A1 * F[1] + A2 * F[2];
         const float B = T * (g[0] * (F[0] - a.bg0) + g[1] * (F[1] - a.bg1) + g[2] * (F[2] - a.bg2));
-        a.b.pixconst[gp] = make_float4(A0, A1, A2, -s1);
-        a.b.pixB[gp] = B;
-        if (a.pre) {
-            const float *pr = a.pre + 9 * pb + local;
-            const float Q1 = pr[7 * HW];
+        pixconst[pb + local] = make_float4(A0, A1, A2, -s1);
+        pixB[pb + local] = B;
+        if constexpr (PRE) {
             // numerator of sum_ch A_ch (P1_ch - F_ch Q1) / sigma^2; divided once below
-            acc += (double)A0 * ((double)pr[3 * HW] - (double)F[0] * Q1) +
-                   (double)A1 * ((double)pr[4 * HW] - (double)F[1] * Q1) +
-                   (double)A2 * ((double)pr[5 * HW] - (double)F[2] * Q1);
+            acc += (double)A0 * ((double)P1[0] - (double)F[0] * Q1) +
+                   (double)A1 * ((double)P1[1] - (double)F[1] * Q1) +
+                   (double)A2 * ((double)P1[2] - (double)F[2] * Q1);
         }
-    }
+    });
     const double t = block_sum_double(acc);
     if (threadIdx.x == 0) {
         const double sig = (double)*a.sigma;
-        a.b.sig_part[blockIdx.x] = a.pre ? t / (sig * sig) : 0.0;
+        a.b.sig_part[blockIdx.x] = PRE ? t / (sig * sig) : 0.0;
     }
 }
 
@@ -171,7 +186,11 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 {
     PixArgs a{b, sigma, bg[0], bg[1], bg[2], pre, grad_image, pixstate, grad_sigma};
     const unsigned blocks = pixel_blocks(b.total_px);
-    if (blocks) hipLaunchKernelGGL(k_pixconst, dim3(blocks), dim3(256), 0, s, a);
+    if (!blocks) return;
+    if (pre)
+        hipLaunchKernelGGL(k_pixconst<true>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_pixconst<false>, dim3(blocks), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------------
