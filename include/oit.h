@@ -395,8 +395,8 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
 
 /*
  * Timing of the raster kernels, for benchmarks.  While enabled (on != 0), every
- * oit_render_fwd launches its raster kernels (the label-change pass when `pre` is
- * given, then the active pass) and every oit_render_bwd its raster kernel with HIP
+ * oit_render_fwd launches its raster kernel (label changes into `pre`, when given,
+ * then the active entries, in one launch) and every oit_render_bwd its raster kernel with HIP
  * events that the runtime records when the kernel starts and when it ends.  Eager
  * launches only: a render call on a stream that is being captured fails with
  * OIT_ERR_INVALID while timing is on.  The events are created once by the first
@@ -406,7 +406,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
 oit_status oit_timing_enable(int32_t on);
 
 /* Wait for the last recorded events; out (host) [2] = milliseconds of the last
- * forward raster kernels (label-change pass plus active pass) and of the last
+ * forward raster kernel and of the last
  * backward raster kernel (-1 if not recorded). */
 oit_status oit_timing_read(float *out);
 

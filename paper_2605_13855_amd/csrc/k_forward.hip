@@ -883,10 +883,17 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
     }
 }
 
-// BAU = true: the label-change pass (blend-and-update of the pre-rendered buffer);
-// it runs first, as its own launch.  BAU = false: the active pass and the image.
-template <int S, int BATCH, bool BAU>
-__global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArgs a)
+// One block per tile.  PRE (a pre-rendered buffer is given): first the label changes
+// are blended into it (BAU: each pixel's sign-weighted deltas are added to its stored
+// accumulators, which are written back) and the pixel keeps the inactive set's terms of
+// the composite in registers; then the active entries are blended (BAN) and the image
+// and the pixel state are written.  Without PRE the active entries are the whole set.
+// With PRE at tile 32 the label changes' accumulators would take 94 registers and hold
+// the whole kernel at five waves per SIMD; at six the compiler keeps them in 80, with a
+// few reloads per batch of records outside the per-record loops.
+template <int S, int BATCH, bool PRE>
+__global__ __launch_bounds__(S * S < 256 ? S * S : 256)
+__attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(FwdArgs a)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     constexpr int PPT = S * S / NT;
@@ -895,9 +902,10 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     constexpr int NW = NT / 64;            // waves (= blocks)
     constexpr int RSTEP = 64 / BW;         // rows between one thread's pixels
     static_assert(NW == WPR * WPR && PPT * RSTEP == BW, "wave blocks must tile the tile");
-    // the active pass stages BATCH records per block; the label-change pass 64 per wave
-    __shared__ float4 s_rec[(BAU ? NW * 64 : BATCH) * 3];
-    __shared__ int s_mask[BAU ? 1 : BATCH];
+    // the active entries are staged BATCH records per block, the label changes 64 per wave
+    constexpr int kStage = PRE && NW * 64 > BATCH ? NW * 64 : BATCH;
+    __shared__ float4 s_rec[kStage * 3];
+    __shared__ int s_mask[BATCH];
 
     const int tile = blockIdx.x;
     const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
@@ -931,10 +939,28 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
     if (off + na + nd > cap) nd = off + na < cap ? cap - off - na : 0;
     const Rec *recv = a.b.rec + (size_t)v * a.b.Rcap;
 
+    const float sigma = *a.sigma;
+    const float isig = 1.f / sigma;
+    // the inactive set's terms of the composite at each pixel (PRE): P0 - P1 / sigma,
+    // Q0 - Q1 / sigma and T = exp(log T), read after the label changes are added
+    float preP[PPT][3], preQ[PPT], preT[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        preP[p][0] = preP[p][1] = preP[p][2] = 0.f;
+        preQ[p] = 0.f;
+        preT[p] = 1.f;
+    }
+
+    // the pixel's stored accumulators -> its inactive-set terms of the composite
+    auto keep_pre = [&](int p, const float (&pv)[9]) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) preP[p][ch] = pv[ch] - pv[3 + ch] * isig;
+        preQ[p] = pv[6] - pv[7] * isig;
+        preT[p] = expf(pv[8]);
+    };
     // label changes: BAU accumulators (sign-weighted, sigma-free), added to the
     // pre-rendered buffer
-    if constexpr (BAU) {
-        if (nd == 0 || a.pre == nullptr) return;
+    if (PRE && nd > 0) {
         // log T changes by sum sign * ln(1 - alpha): the factors of each sign are
         // multiplied (Tp: +1, Tm: -1) and folded into dL every kFold records, before
         // a product of factors >= 1 - kAlphaMax can underflow
@@ -1003,10 +1029,27 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
             float *pr = a.pre + 9 * pb + pix;
             const float add[9] = {dP0[p][0], dP0[p][1], dP0[p][2], dP1[p][0], dP1[p][1],
                                   dP1[p][2], dQ0[p],    dQ1[p],    dL[p]};
+            float pv[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) pr[k * HW] += add[k];
+            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                pv[k] += add[k];
+                pr[k * HW] = pv[k];
+            }
+            keep_pre(p, pv);
         }
-        return;
+    } else if (PRE) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            if (!in[p]) continue;
+            const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
+            const float *pr = a.pre + 9 * pb + pix;
+            float pv[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
+            keep_pre(p, pv);
+        }
     }
 
     // active entries: BAN accumulators
@@ -1054,23 +1097,17 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_fwd(FwdArg
         }
     }
 
-    const float sigma = *a.sigma;
-    const float isig = 1.f / sigma;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         if (!in[p]) continue;
         const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
         float Pt[3] = {P[p][0], P[p][1], P[p][2]};
         float Qt = Q[p], Tt = T[p];
-        if (a.pre) {
-            const float *pr = a.pre + 9 * pb + pix;
-            float pv[9];
+        if constexpr (PRE) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) Pt[ch] += pv[ch] - pv[3 + ch] * isig;
-            Qt += pv[6] - pv[7] * isig;
-            Tt *= expf(pv[8]);
+            for (int ch = 0; ch < 3; ++ch) Pt[ch] += preP[p][ch];
+            Qt += preQ[p];
+            Tt *= preT[p];
         }
         const float iq = Qt > 0.f ? 1.f / Qt : 0.f;
         const float F0 = Pt[0] * iq, F1 = Pt[1] * iq, F2 = Pt[2] * iq;
@@ -1096,16 +1133,16 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const K
         hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
 }
 
-template <int S, bool BAU>
+template <int S, bool PRE>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
-    case 32: launch_timed(k_raster_fwd<S, 32, BAU>, grid, block, s, t, a); return true;
-    case 64: launch_timed(k_raster_fwd<S, 64, BAU>, grid, block, s, t, a); return true;
-    case 128: launch_timed(k_raster_fwd<S, 128, BAU>, grid, block, s, t, a); return true;
-    case 256: launch_timed(k_raster_fwd<S, 256, BAU>, grid, block, s, t, a); return true;
+    case 32: launch_timed(k_raster_fwd<S, 32, PRE>, grid, block, s, t, a); return true;
+    case 64: launch_timed(k_raster_fwd<S, 64, PRE>, grid, block, s, t, a); return true;
+    case 128: launch_timed(k_raster_fwd<S, 128, PRE>, grid, block, s, t, a); return true;
+    case 256: launch_timed(k_raster_fwd<S, 256, PRE>, grid, block, s, t, a); return true;
     default: return false;
     }
 }
@@ -1136,23 +1173,23 @@ __global__ __launch_bounds__(1024) void k_pair_totals(Buffers b)
 }
 
 template <int S>
-static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s, const KTimer *bau_t, const KTimer *fwd_t)
+static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s, const KTimer *fwd_t)
 {
-    if (a.pre && !raster_fwd_s<S, true>(a, batch, s, bau_t)) return false;
-    if (!raster_fwd_s<S, false>(a, batch, s, fwd_t)) return false;
+    if (!(a.pre ? raster_fwd_s<S, true>(a, batch, s, fwd_t) : raster_fwd_s<S, false>(a, batch, s, fwd_t)))
+        return false;
     hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(1024), 0, s, a.b);
     return true;
 }
 
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s, const KTimer *bau_t, const KTimer *fwd_t)
+                       float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t)
 {
     FwdArgs a{b, sigma, bg[0], bg[1], bg[2], pre, image, pixstate};
     if (b.T == 0) return true;
     switch (b.tile) {
-    case 8: return raster_fwd_both<8>(a, batch, s, bau_t, fwd_t);
-    case 16: return raster_fwd_both<16>(a, batch, s, bau_t, fwd_t);
-    case 32: return raster_fwd_both<32>(a, batch, s, bau_t, fwd_t);
+    case 8: return raster_fwd_both<8>(a, batch, s, fwd_t);
+    case 16: return raster_fwd_both<16>(a, batch, s, fwd_t);
+    case 32: return raster_fwd_both<32>(a, batch, s, fwd_t);
     default: return false;
     }
 }

@@ -17,11 +17,10 @@ namespace {
 thread_local char g_err[512] = "";
 
 // optional timing of the raster kernels (see oit_timing_enable): start/stop events of
-// the label-change pass, the active forward pass and the backward
-hipEvent_t g_ev[6];
+// the forward and of the backward
+hipEvent_t g_ev[4];
 bool g_timing_ready = false;
 bool g_timing_on = false;
-bool g_bau_timed = false;   // the last forward launched the label-change pass
 
 
 oit_status fail(oit_status st, const char *fmt, ...)
@@ -352,11 +351,9 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
     launch_binning(rl, b, s);
-    const KTimer bau_t{g_ev[0], g_ev[1]}, fwd_t{g_ev[2], g_ev[3]};
-    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s, g_timing_on ? &bau_t : nullptr,
-                           g_timing_on ? &fwd_t : nullptr))
+    const KTimer fwd_t{g_ev[0], g_ev[1]};
+    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s, g_timing_on ? &fwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
-    if (g_timing_on) g_bau_timed = pre != nullptr;
     return check_launch("oit_render_fwd");
 }
 
@@ -477,7 +474,7 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
     fill_u32(b.counters + CNT_BOX_ITEMS, 1, 0u, s);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
-    const KTimer bwd_t{g_ev[4], g_ev[5]};
+    const KTimer bwd_t{g_ev[2], g_ev[3]};
     if (!launch_raster_bwd(b, rl, s, g_timing_on ? &bwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
     launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
@@ -730,7 +727,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
 oit_status oit_timing_enable(int32_t on)
 {
     if (on && !g_timing_ready) {
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const hipError_t e = hipEventCreate(&g_ev[k]);
             if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_timing_enable: %s", hipGetErrorString(e));
         }
@@ -744,15 +741,12 @@ oit_status oit_timing_read(float *out)
 {
     if (!out) return fail(OIT_ERR_INVALID, "oit_timing_read: NULL output");
     if (!g_timing_ready) return fail(OIT_ERR_INVALID, "oit_timing_read: timing was never enabled");
-    float ms[3] = {0.f, 0.f, 0.f};
-    for (int k = 0; k < 3; ++k) {
-        if (k == 0 && !g_bau_timed) continue;
+    for (int k = 0; k < 2; ++k) {
+        float ms = 0.f;
         hipError_t e = hipEventSynchronize(g_ev[2 * k + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms[k], g_ev[2 * k], g_ev[2 * k + 1]);
-        if (e != hipSuccess) ms[k] = -1.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_ev[2 * k], g_ev[2 * k + 1]);
+        out[k] = e == hipSuccess ? ms : -1.f;
     }
-    out[0] = ms[0] < 0.f || ms[1] < 0.f ? -1.f : ms[0] + ms[1];
-    out[1] = ms[2];
     return ok();
 }
 

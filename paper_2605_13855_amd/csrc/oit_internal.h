@@ -111,8 +111,7 @@ struct KTimer {
 };
 
 bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s, const KTimer *bau_t = nullptr,
-                       const KTimer *fwd_t = nullptr);
+                       float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t = nullptr);
 
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s);
