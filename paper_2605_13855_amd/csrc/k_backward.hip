@@ -877,7 +877,6 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
 {
     __shared__ float s_geo[kPbThreads][10];   // g_mu, G6, g_lo
     __shared__ float s_app[kPbThreads][20];   // gcm (3), gvm, Y (16)
-    __shared__ float s_n2[kPbThreads][2];     // partial squared norms of the sh / vsh outputs
     const int P = a.vlanes, V = a.b.n_views;
     const int rows_per_block = kPbThreads / P;
     const int lr = threadIdx.x / P, vl = threadIdx.x % P;
@@ -957,9 +956,12 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
                 nvsh += acc * acc;
             }
         }
-        s_n2[threadIdx.x][0] = nsh;
-        s_n2[threadIdx.x][1] = nvsh;
-        __syncthreads();
+        // the row's squared norms of the sh / vsh outputs: a butterfly over its P lanes
+        // (P divides 64, so a row's lanes are within one wave)
+        for (int o = 1; o < P; o <<= 1) {
+            nsh += __shfl_xor(nsh, o);
+            nvsh += __shfl_xor(nvsh, o);
+        }
         if (row_ok && vl == 0) {
             float g_mu[3] = {0.f, 0.f, 0.f}, G6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, g_lo = 0.f;
             float n2[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -970,10 +972,8 @@ __global__ __launch_bounds__(kPbThreads) void k_preprocess_bwd(PreBwdArgs a)
                 for (int k = 0; k < 6; ++k) G6[k] += s_geo[g0 + u][3 + k];
                 g_lo += s_geo[g0 + u][9];
             }
-            for (int u = 0; u < P; ++u) {
-                n2[4] += s_n2[g0 + u][0];
-                n2[5] += s_n2[g0 + u][1];
-            }
+            n2[4] = nsh;
+            n2[5] = nvsh;
             // Sigma = M M^T, M = Rq diag(s):  dL/dM = 2 G M
             const float Gf[9] = {G6[0], G6[1], G6[2], G6[1], G6[3], G6[4], G6[2], G6[4], G6[5]};
             float gRq[9], g_ls[3];

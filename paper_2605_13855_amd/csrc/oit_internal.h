@@ -19,7 +19,7 @@ constexpr int kRadixBits = 5;                  // digit width of a radix-sort pa
 constexpr int kRadixBuckets = 1 << kRadixBits;
 constexpr int kSizeBits = 5;                   // footprint-size class below (tile, class) in the sort key
 constexpr int kSigPixParts = 2048;             // blocks of the per-pixel backward kernels (at most)
-constexpr int kSigPreParts = 1024;             // blocks of the preprocess backward (at most)
+constexpr int kSigPreParts = 4096;             // blocks of the preprocess backward (at most)
 
 // counters[] slots in the workspace
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
