@@ -136,8 +136,8 @@ def test_config3_dense_and_active_sampled():
 
 def test_config4_batched_active_sampled():
     sc = scenes.make_scene(4)
-    log("config 4, 5% active, 16 uneven views in one launch")
-    run_case(sc, 24, 5, active_fraction=0.05)
+    log("config 4, 5% active, 16 uneven views in one launch (tile 32, batch 64: the benchmark's launch)")
+    run_case(sc, 24, 5, active_fraction=0.05, tile=32)
 
 
 def test_config5_clusters_sampled():
