@@ -40,16 +40,25 @@ __device__ __forceinline__ double block_sum_double(double v)
 }
 
 // dL/dsigma: the per-block shares of the pixel constants' pass (inactive set) and of the
-// preprocess backward, added in block order by one wave, so that the result does not
-// depend on the order in which blocks finish.
-__global__ void k_sigma_total(const double *part, int npix, int npre, double *grad_sigma)
+// preprocess backward, added in a fixed order by one block (each thread a fixed strided
+// subset, then a tree in LDS), so that the result does not depend on the order in which
+// the blocks that wrote them finished.
+constexpr int kSigThreads = 1024;
+
+__global__ __launch_bounds__(kSigThreads) void k_sigma_total(const double *part, int npix, int npre,
+                                                             double *grad_sigma)
 {
-    const int lane = threadIdx.x;
+    __shared__ double s_t[kSigThreads];
     double t = 0.0;
-    for (int i = lane; i < npix; i += 64) t += part[i];
-    for (int i = lane; i < npre; i += 64) t += part[kSigPixParts + i];
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0) *grad_sigma = t;
+    for (int i = threadIdx.x; i < npix; i += kSigThreads) t += part[i];
+    for (int i = threadIdx.x; i < npre; i += kSigThreads) t += part[kSigPixParts + i];
+    s_t[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = kSigThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s_t[threadIdx.x] += s_t[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *grad_sigma = s_t[0];
 }
 
 // The pixels gp = tid, tid + stride, ... of the batch, as a flat grid-stride loop visits
@@ -1055,7 +1064,7 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
     int64_t blocks = (rl.Acap + rows_per_block - 1) / rows_per_block;
     if (blocks > kPbBlocks) blocks = kPbBlocks;
     if (blocks > 0) hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)blocks), dim3(kPbThreads), 0, s, a);
-    hipLaunchKernelGGL(k_sigma_total, dim3(1), dim3(64), 0, s, (const double *)b.sig_part,
+    hipLaunchKernelGGL(k_sigma_total, dim3(1), dim3(kSigThreads), 0, s, (const double *)b.sig_part,
                        (int)pixel_blocks(b.total_px), (int)blocks, grad_sigma);
 }
 
