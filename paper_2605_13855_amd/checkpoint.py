@@ -143,6 +143,7 @@ def load(trainer, path):
         trainer.view_epoch = [int(x) for x in meta["view_epoch"]]
         trainer.last_update_views = [int(x) for x in meta["last_update_views"]]
         trainer.rebuilds = int(meta["rebuilds"])
+        trainer.idx_epoch = None   # active_idx is not in the checkpoint: the next view rebuilds it
         trainer.grads = new_grads(n, dev)
     cap = int(meta["pair_capacity"])
     if cap > trainer.r.tuning.pair_capacity:

@@ -883,18 +883,21 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
     }
 }
 
-// One block per tile.  PRE (a pre-rendered buffer is given): first the label changes
-// are blended into it (BAU: each pixel's sign-weighted deltas are added to its stored
-// accumulators, which are written back) and the pixel keeps the inactive set's terms of
-// the composite in registers; then the active entries are blended (BAN) and the image
-// and the pixel state are written.  Without PRE the active entries are the whole set.
-// With PRE at tile 32 the label changes' accumulators would take 94 registers and hold
-// the whole kernel at five waves per SIMD; at six the compiler keeps them in 80, with a
-// few reloads per batch of records outside the per-record loops.
-template <int S, int BATCH, bool PRE>
+// One block per tile.  PRE (a pre-rendered buffer is given): the pixel reads the
+// inactive set's terms of the composite from it, and with BAU (the call lists label
+// changes) the label changes are first blended into it (each pixel's sign-weighted
+// deltas are added to its stored accumulators, which are written back).  Then the
+// active entries are blended (BAN) and the image and the pixel state are written.
+// Without PRE the active entries are the whole set.  With BAU at tile 32 the label
+// changes' accumulators would take 94 registers and hold the whole kernel at five waves
+// per SIMD; at six the compiler keeps them in 80, with a few reloads per batch of
+// records outside the per-record loops.  A call without a label-change list takes the
+// variant without them, which keeps the active part's eight waves.
+template <int S, int BATCH, bool PRE, bool BAU>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256)
-__attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(FwdArgs a)
+__attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(FwdArgs a)
 {
+    static_assert(PRE || !BAU, "label changes go into a pre-rendered buffer");
     constexpr int NT = S * S < 256 ? S * S : 256;
     constexpr int PPT = S * S / NT;
     constexpr int BW = S == 32 ? 16 : 8;   // edge of a wave's pixel block
@@ -903,7 +906,7 @@ __attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(F
     constexpr int RSTEP = 64 / BW;         // rows between one thread's pixels
     static_assert(NW == WPR * WPR && PPT * RSTEP == BW, "wave blocks must tile the tile");
     // the active entries are staged BATCH records per block, the label changes 64 per wave
-    constexpr int kStage = PRE && NW * 64 > BATCH ? NW * 64 : BATCH;
+    constexpr int kStage = BAU && NW * 64 > BATCH ? NW * 64 : BATCH;
     __shared__ float4 s_rec[kStage * 3];
     __shared__ int s_mask[BATCH];
 
@@ -960,7 +963,7 @@ __attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(F
     };
     // label changes: BAU accumulators (sign-weighted, sigma-free), added to the
     // pre-rendered buffer
-    if (PRE && nd > 0) {
+    if (BAU && nd > 0) {
         // log T changes by sum sign * ln(1 - alpha): the factors of each sign are
         // multiplied (Tp: +1, Tm: -1) and folded into dL every kFold records, before
         // a product of factors >= 1 - kAlphaMax can underflow
@@ -1039,7 +1042,7 @@ __attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(F
             }
             keep_pre(p, pv);
         }
-    } else if (PRE) {
+    } else if (BAU) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (!in[p]) continue;
@@ -1104,6 +1107,15 @@ __attribute__((amdgpu_waves_per_eu(PRE && S == 32 ? 6 : 1))) void k_raster_fwd(F
         float Pt[3] = {P[p][0], P[p][1], P[p][2]};
         float Qt = Q[p], Tt = T[p];
         if constexpr (PRE) {
+            if constexpr (!BAU) {
+                // without label changes the stored terms are read here, after the active
+                // entries, so that they are not live across the active loop
+                const float *pr = a.pre + 9 * pb + pix;
+                float pv[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
+                keep_pre(p, pv);
+            }
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) Pt[ch] += preP[p][ch];
             Qt += preQ[p];
@@ -1133,16 +1145,16 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const K
         hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
 }
 
-template <int S, bool PRE>
+template <int S, bool PRE, bool BAU>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
     const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
-    case 32: launch_timed(k_raster_fwd<S, 32, PRE>, grid, block, s, t, a); return true;
-    case 64: launch_timed(k_raster_fwd<S, 64, PRE>, grid, block, s, t, a); return true;
-    case 128: launch_timed(k_raster_fwd<S, 128, PRE>, grid, block, s, t, a); return true;
-    case 256: launch_timed(k_raster_fwd<S, 256, PRE>, grid, block, s, t, a); return true;
+    case 32: launch_timed(k_raster_fwd<S, 32, PRE, BAU>, grid, block, s, t, a); return true;
+    case 64: launch_timed(k_raster_fwd<S, 64, PRE, BAU>, grid, block, s, t, a); return true;
+    case 128: launch_timed(k_raster_fwd<S, 128, PRE, BAU>, grid, block, s, t, a); return true;
+    case 256: launch_timed(k_raster_fwd<S, 256, PRE, BAU>, grid, block, s, t, a); return true;
     default: return false;
     }
 }
@@ -1173,23 +1185,25 @@ __global__ __launch_bounds__(1024) void k_pair_totals(Buffers b)
 }
 
 template <int S>
-static bool raster_fwd_both(const FwdArgs &a, int batch, hipStream_t s, const KTimer *fwd_t)
+static bool raster_fwd_both(const FwdArgs &a, bool deltas, int batch, hipStream_t s, const KTimer *fwd_t)
 {
-    if (!(a.pre ? raster_fwd_s<S, true>(a, batch, s, fwd_t) : raster_fwd_s<S, false>(a, batch, s, fwd_t)))
-        return false;
+    const bool ok = !a.pre   ? raster_fwd_s<S, false, false>(a, batch, s, fwd_t)
+                    : deltas ? raster_fwd_s<S, true, true>(a, batch, s, fwd_t)
+                             : raster_fwd_s<S, true, false>(a, batch, s, fwd_t);
+    if (!ok) return false;
     hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(1024), 0, s, a.b);
     return true;
 }
 
-bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t)
+bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, bool deltas,
+                       float *image, float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t)
 {
     FwdArgs a{b, sigma, bg[0], bg[1], bg[2], pre, image, pixstate};
     if (b.T == 0) return true;
     switch (b.tile) {
-    case 8: return raster_fwd_both<8>(a, batch, s, fwd_t);
-    case 16: return raster_fwd_both<16>(a, batch, s, fwd_t);
-    case 32: return raster_fwd_both<32>(a, batch, s, fwd_t);
+    case 8: return raster_fwd_both<8>(a, deltas, batch, s, fwd_t);
+    case 16: return raster_fwd_both<16>(a, deltas, batch, s, fwd_t);
+    case 32: return raster_fwd_both<32>(a, deltas, batch, s, fwd_t);
     default: return false;
     }
 }

@@ -352,7 +352,8 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
     launch_binning(rl, b, s);
     const KTimer fwd_t{g_ev[0], g_ev[1]};
-    if (!launch_raster_fwd(b, sigma, bg, pre, image, pixstate, tuning->batch, s, g_timing_on ? &fwd_t : nullptr))
+    if (!launch_raster_fwd(b, sigma, bg, pre, delta_idx != nullptr, image, pixstate, tuning->batch, s,
+                           g_timing_on ? &fwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
     return check_launch("oit_render_fwd");
 }

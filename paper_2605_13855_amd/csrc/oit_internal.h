@@ -110,8 +110,9 @@ struct KTimer {
     hipEvent_t start, stop;
 };
 
-bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, float *image,
-                       float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t = nullptr);
+// deltas: the call lists label changes (their entries are blended into pre first)
+bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], float *pre, bool deltas,
+                       float *image, float *pixstate, int batch, hipStream_t s, const KTimer *fwd_t = nullptr);
 
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s);

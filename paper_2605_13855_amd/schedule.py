@@ -69,6 +69,7 @@ class PaperScheduleTrainer:
         self.active_idx = torch.zeros(n, dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
         self.delta_idx = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.idx_epoch = None   # the epoch whose active list active_idx holds (None: unknown)
         self.delta_sign = torch.zeros(n, dtype=torch.int8, device=dev)
         self.n_delta = torch.zeros(1, dtype=torch.int32, device=dev)
         self.sel_ws = _aligned_workspace(oit.select_workspace_bytes(n), dev)
@@ -108,6 +109,7 @@ class PaperScheduleTrainer:
                               self.n_active, self.delta_idx, self.delta_sign, self.n_delta, self.sel_ws)
         self.epoch += 1
         self.labels[self.epoch] = new_label
+        self.idx_epoch = self.epoch
         # every splat whose label differs between two consecutive epochs is frozen at this
         # moment: these are the values it was (or will be) added to a pre buffer with
         for g, p in self.params.items():
@@ -129,6 +131,10 @@ class PaperScheduleTrainer:
         """Active list of the current labels and the label changes that bring view v's
         pre-rendered buffer up to date (rebuilding it if it is two updates behind)."""
         old = self.view_epoch[v]
+        if old == self.epoch and self.idx_epoch == self.epoch:
+            # the view's buffer is up to date and active_idx holds the current labels'
+            # list: no label changes (the forward then keeps its active part's occupancy)
+            return {"idx": self.active_idx, "n": self.n_active}
         if old < self.epoch - 1:
             self.pre[v].zero_()
             old_label = self.all_active
@@ -137,6 +143,7 @@ class PaperScheduleTrainer:
             old_label = self.labels[old]
         oit.label_delta(old_label, self.labels[self.epoch], self.n, self.active_idx, self.n_active, self.delta_idx,
                         self.delta_sign, self.n_delta, self.sel_ws)
+        self.idx_epoch = self.epoch
         return {"idx": self.active_idx, "n": self.n_active, "delta_idx": self.delta_idx,
                 "delta_sign": self.delta_sign, "n_delta": self.n_delta}
 

@@ -421,6 +421,30 @@ def test_active_set_render_equals_dense():
     assert torch.equal(r3.image, r2.image)
     assert torch.equal(pre_before, pre)
 
+    # step 4: pre is up to date; the same active list with no label-change list takes the
+    # forward's variant without label changes: the same image bit for bit, pre untouched,
+    # and at tile 32 the dense image within tolerance
+    act4 = {"idx": act2["idx"], "n": act2["n"]}
+    img2 = r2.image.clone()
+    pre_now = pre.clone()
+    r2.forward(params, sigma, sc.background, act4, pre)
+    torch.cuda.synchronize()
+    assert r2.status() == 0
+    assert torch.equal(pre, pre_now)
+    assert torch.equal(r2.image, img2)
+    r4 = Renderer(sc.cameras, n, active_capacity=k, tile=32, batch=64)
+    r4.fit_pair_capacity(params, sigma, sc.background, act4, pre)
+    r4.forward(params, sigma, sc.background, act4, pre)
+    torch.cuda.synchronize()
+    assert r4.status() == 0
+    assert torch.equal(pre, pre_now)
+    imgs4 = image_views(r4, r4.image, 3)
+    for v, cam in enumerate(sc.cameras):
+        dense = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)
+        err = compare_image(imgs4[v], dense["image"], dense["near"])
+        log(f"  no label-change list, tile 32, view {v}: err {err:.2e}")
+        assert err <= IMAGE_RTOL
+
 
 def test_pair_overflow_is_reported_and_bounded():
     sc = scenes.make_scene(1)
