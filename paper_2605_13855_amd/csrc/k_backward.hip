@@ -490,8 +490,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     if (valid) write_partials(dst, qa, qb, qc, w, o);
 }
 
+// Six waves per SIMD: the kernel then keeps its 78 registers without spilling; held to
+// eight (64 registers) it spilled in the walks and ran 4-6% slower.
 template <int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_raster_bwd(BwdArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_bwd(BwdArgs a)
 {
     __shared__ float4 s_c[4][64];
     __shared__ float s_B[4][64];
