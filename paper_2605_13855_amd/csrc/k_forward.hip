@@ -945,7 +945,8 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
     const float sigma = *a.sigma;
     const float isig = 1.f / sigma;
     // the inactive set's terms of the composite at each pixel (PRE): P0 - P1 / sigma,
-    // Q0 - Q1 / sigma and T = exp(log T), read after the label changes are added
+    // Q0 - Q1 / sigma and T = exp(log T); with BAU read here, once the label changes
+    // are added, without it read after the active entries
     float preP[PPT][3], preQ[PPT], preT[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
