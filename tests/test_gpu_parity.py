@@ -464,7 +464,7 @@ def test_pair_overflow_is_reported_and_bounded():
 def test_forward_and_backward_are_run_to_run_reproducible():
     """The tile lists come from a stable sort, the backward has no atomics and dL/dsigma
     adds its block shares in a fixed order: two calls on the same inputs give bitwise
-    equal images, states and gradients, sigma's included."""
+    equal images, states and gradients, sigma's included (dense, then active set)."""
     sc = scenes.make_scene(2)
     params = params_to_device(sc.params)
     sigma = torch.tensor([sc.sigma], device=DEV)
@@ -485,6 +485,35 @@ def test_forward_and_backward_are_run_to_run_reproducible():
     assert torch.equal(i0, i1) and torch.equal(s0, s1)
     for k in g0:
         assert torch.equal(g0[k], g1[k]), k
+    assert torch.equal(q0, q1)
+
+    # the active-set path at the same tiling: label changes folded into a pre-rendered
+    # buffer by the one-launch forward, then the backward restricted to the active rows
+    n = sc.n
+    k = max(1, n // 20)
+    idx, didx, dsg, _ = run_select(torch.rand(n, device=DEV), torch.ones(n, dtype=torch.uint8, device=DEV), k)
+    act = {"idx": torch.tensor(idx, dtype=torch.int32, device=DEV),
+           "n": torch.tensor([len(idx)], dtype=torch.int32, device=DEV),
+           "delta_idx": torch.tensor(didx, dtype=torch.int32, device=DEV),
+           "delta_sign": torch.tensor(dsg, dtype=torch.int8, device=DEV),
+           "n_delta": torch.tensor([len(didx)], dtype=torch.int32, device=DEV)}
+    total_px = sum(c.width * c.height for c in sc.cameras)
+    ra = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx), 1), tile=32, batch=64)
+    ra.fit_pair_capacity(params, sigma, sc.background, act, torch.zeros(9 * total_px, device=DEV))
+    outs = []
+    for _ in range(2):
+        pre = torch.zeros(9 * total_px, device=DEV)
+        ra.forward(params, sigma, sc.background, act, pre)
+        g = new_grads(k, DEV)
+        gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+        ra.backward(params, sigma, sc.background, gimg, g, gsig, act, pre)
+        torch.cuda.synchronize()
+        outs.append((ra.image.clone(), pre, {kk: v.clone() for kk, v in g.items()}, gsig.clone()))
+    assert ra.status() == 0
+    (i0, p0, g0, q0), (i1, p1, g1, q1) = outs
+    assert torch.equal(i0, i1) and torch.equal(p0, p1)
+    for kk in g0:
+        assert torch.equal(g0[kk], g1[kk]), kk
     assert torch.equal(q0, q1)
 
 
