@@ -7,22 +7,6 @@
 
 namespace oit {
 
-// Sum of a double over the block, added once to *dst.
-__device__ __forceinline__ void block_add_double(double v, double *dst)
-{
-    __shared__ double s_part[16];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) s_part[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int w = 0; w < nw; ++w) t += s_part[w];
-        if (t != 0.0) unsafeAtomicAdd(dst, t);
-    }
-}
-
 // The block's sum of v, on thread 0 (fixed order: lanes by a butterfly, waves in turn).
 __device__ __forceinline__ double block_sum_double(double v)
 {
@@ -39,26 +23,27 @@ __device__ __forceinline__ double block_sum_double(double v)
     return t;
 }
 
-// dL/dsigma: the per-block shares of the pixel constants' pass (inactive set) and of the
-// preprocess backward, added in a fixed order by one block (each thread a fixed strided
-// subset, then a tree in LDS), so that the result does not depend on the order in which
-// the blocks that wrote them finished.
-constexpr int kSigThreads = 1024;
+// A sum of per-block shares (dL/dsigma: those of the pixel constants' pass, the inactive
+// set, then those of the preprocess backward; the L1 loss: those of its pass), added in a
+// fixed order by one block (each thread a fixed strided subset, then a tree in LDS), so
+// that the result does not depend on the order in which the blocks that wrote them
+// finished.
+constexpr int kSumThreads = 1024;
 
-__global__ __launch_bounds__(kSigThreads) void k_sigma_total(const double *part, int npix, int npre,
-                                                             double *grad_sigma)
+__global__ __launch_bounds__(kSumThreads) void k_sum_shares(const double *a, int na, const double *b, int nb,
+                                                            double *dst)
 {
-    __shared__ double s_t[kSigThreads];
+    __shared__ double s_t[kSumThreads];
     double t = 0.0;
-    for (int i = threadIdx.x; i < npix; i += kSigThreads) t += part[i];
-    for (int i = threadIdx.x; i < npre; i += kSigThreads) t += part[kSigPixParts + i];
+    for (int i = threadIdx.x; i < na; i += kSumThreads) t += a[i];
+    for (int i = threadIdx.x; i < nb; i += kSumThreads) t += b[i];
     s_t[threadIdx.x] = t;
     __syncthreads();
-    for (int o = kSigThreads / 2; o > 0; o >>= 1) {
+    for (int o = kSumThreads / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) s_t[threadIdx.x] += s_t[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *grad_sigma = s_t[0];
+    if (threadIdx.x == 0) *dst = s_t[0];
 }
 
 // The pixels gp = tid, tid + stride, ... of the batch, as a flat grid-stride loop visits
@@ -117,16 +102,18 @@ __global__ __launch_bounds__(256) void k_l1_loss(LossArgs a)
             acc += fabs((double)d) * dinv;
         }
     });
-    block_add_double(acc, a.loss);
+    const double t = block_sum_double(acc);
+    if (threadIdx.x == 0) a.b.loss_part[blockIdx.x] = t;
 }
 
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s)
 {
-    fill_f64(loss, 1, 0.0, s);
     LossArgs a{b, image, target, grad, loss};
     const unsigned blocks = pixel_blocks(b.total_px);
     if (blocks) hipLaunchKernelGGL(k_l1_loss, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sum_shares, dim3(1), dim3(kSumThreads), 0, s, (const double *)b.loss_part, (int)blocks,
+                       (const double *)nullptr, 0, loss);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1066,8 +1053,9 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
     int64_t blocks = (rl.Acap + rows_per_block - 1) / rows_per_block;
     if (blocks > kPbBlocks) blocks = kPbBlocks;
     if (blocks > 0) hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)blocks), dim3(kPbThreads), 0, s, a);
-    hipLaunchKernelGGL(k_sigma_total, dim3(1), dim3(kSigThreads), 0, s, (const double *)b.sig_part,
-                       (int)pixel_blocks(b.total_px), (int)blocks, grad_sigma);
+    hipLaunchKernelGGL(k_sum_shares, dim3(1), dim3(kSumThreads), 0, s, (const double *)b.sig_part,
+                       (int)pixel_blocks(b.total_px), (const double *)(b.sig_part + kSigPixParts), (int)blocks,
+                       grad_sigma);
 }
 
 }  // namespace oit

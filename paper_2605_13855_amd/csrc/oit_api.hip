@@ -61,7 +61,7 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
     size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, orig, keys0, keys1, vals0,
-        vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, sig_part,
+        vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, sig_part, loss_part,
         tile_cnt, total;
     uint32_t max_chunks;
     int T;
@@ -187,6 +187,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
     p.sig_part = o; o = align256(o + 8 * (size_t)(kSigPixParts + kSigPreParts));
+    p.loss_part = o; o = align256(o + 8 * (size_t)kSigPixParts);
     p.tile_cnt = o; o = align256(o + 16 * (size_t)p.T);
     p.total = o;
     return OIT_OK;
@@ -224,6 +225,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.pixconst = (float4 *)(w + p.pixconst);
     b.pixB = (float *)(w + p.pixB);
     b.sig_part = (double *)(w + p.sig_part);
+    b.loss_part = (double *)(w + p.loss_part);
     b.tile_cnt = (unsigned long long *)(w + p.tile_cnt);
     b.n_views = n_views;
     b.T = p.T;

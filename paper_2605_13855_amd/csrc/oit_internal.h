@@ -78,6 +78,7 @@ struct Buffers {
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
     float *pixB;                                // [total_px] B
     double *sig_part;                           // [kSigPixParts + kSigPreParts] per-block shares of dL/dsigma
+    double *loss_part;                          // [kSigPixParts] per-block shares of the L1 loss
     unsigned long long *tile_cnt;               // [T][2] contributing / evaluated active pairs per tile
     uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
