@@ -166,10 +166,23 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
                           void *ws, size_t ws_bytes, const oit_tuning *tuning, oit_stream stream);
 
 /*
+ * Bytes of workspace that oit_l1_loss needs (a constant: a status word, the camera
+ * table and 2048 FP64 per-block shares of the loss value).  Every render workspace
+ * (oit_workspace_bytes) begins with this head in the same layout, so a render
+ * workspace may be passed to oit_l1_loss between oit_render_fwd and oit_render_bwd:
+ * the loss writes only the head, which oit_render_bwd does not read back (it uploads
+ * its cameras again).
+ */
+size_t oit_l1_loss_workspace_bytes(void);
+
+/*
  * L1 photometric loss over the batch (the L1 term of the 3DGS loss that the paper
  * keeps, Sec. 5.1): loss = sum_views mean_{3 H W} |C - target| and
  * grad_image = sign(C - target) / (3 H W) per view (sign(0) = 0).
- * image, target, grad_image [V][3][H][W]; loss [1] device double (overwritten).
+ * image, target, grad_image [V][3][H][W]; loss [1] device double (overwritten), the
+ * blocks' shares added in a fixed order.
+ * ws          at least oit_l1_loss_workspace_bytes() bytes, 256-byte aligned (a render
+ *             workspace qualifies, see above); OIT_ERR_WORKSPACE if smaller.
  */
 oit_status oit_l1_loss(const float *image, const float *target, const oit_camera *cams,
                        int32_t n_views, float *grad_image, double *loss,

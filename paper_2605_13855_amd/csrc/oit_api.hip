@@ -155,8 +155,10 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.Acap = cap->active_capacity;
     p.Rcap = cap->active_capacity + cap->delta_capacity;
     size_t o = 0;
+    // head shared with oit_l1_loss's layout: status word, camera table, loss shares
     p.status = o; o = align256(o + 4);
     p.cams = o; o = align256(o + sizeof(CamDev) * kMaxViews);
+    p.loss_part = o; o = align256(o + 8 * (size_t)kSigPixParts);
     p.counters = o; o = align256(o + 4 * CNT_SLOTS);
     p.tiles = o; o = align256(o + 4 * 2 * (size_t)p.T);
     p.tile_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
@@ -187,7 +189,6 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
     p.sig_part = o; o = align256(o + 8 * (size_t)(kSigPixParts + kSigPreParts));
-    p.loss_part = o; o = align256(o + 8 * (size_t)kSigPixParts);
     p.tile_cnt = o; o = align256(o + 16 * (size_t)p.T);
     p.total = o;
     return OIT_OK;
@@ -315,9 +316,27 @@ SelectBuffers select_buffers(void *ws, int64_t n)
     return sb;
 }
 
+// The L1 loss's plan: the cameras' table and pixel bases of a render plan; it touches
+// only the head of the layout (status word, camera table, loss shares), at the same
+// offsets as every render plan, so a render workspace can be passed to it between the
+// forward and the backward pass.
+constexpr oit_tuning kL1Tuning{16, 64, 1, OIT_BWD_PER_SPLAT, 0};
+
+oit_status l1_plan(const oit_camera *cams, int32_t n_views, Plan &p)
+{
+    const oit_capacity cap{1, 1, 0};
+    return make_plan(&cap, cams, n_views, &kL1Tuning, p);
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t oit_l1_loss_workspace_bytes(void)
+{
+    // the head of every render layout: status word, camera table, the loss's block shares
+    return align256(align256(align256(4) + sizeof(CamDev) * kMaxViews) + 8 * (size_t)kSigPixParts);
+}
 
 size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int32_t n_views,
                            const oit_tuning *tuning)
@@ -367,15 +386,12 @@ oit_status oit_l1_loss(const float *image, const float *target, const oit_camera
     if ((st = check_cams(cams, n_views)) != OIT_OK) return st;
     if (!image || !target || !grad_image || !loss) return fail(OIT_ERR_INVALID, "oit_l1_loss: NULL buffer");
     if (!ws || !aligned(ws, 256)) return fail(OIT_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
-    // the loss only needs the camera table at the head of the workspace
-    const size_t need = align256(4) + sizeof(CamDev) * kMaxViews;
+    const size_t need = oit_l1_loss_workspace_bytes();
     if (ws_bytes < need) return fail(OIT_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    oit_capacity cap{1, 1, 0};
-    oit_tuning tu{16, 64, 1, OIT_BWD_PER_SPLAT, 0};
     Plan p;
-    if ((st = make_plan(&cap, cams, n_views, &tu, p)) != OIT_OK) return st;
+    if ((st = l1_plan(cams, n_views, p)) != OIT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    Buffers b = buffers(p, ws, n_views, &tu);
+    Buffers b = buffers(p, ws, n_views, &kL1Tuning);
     upload_cams(p.cams_host, n_views, b.cams, s);
     launch_l1_loss(b, image, target, grad_image, loss, s);
     return check_launch("oit_l1_loss");

@@ -69,6 +69,8 @@ def _load():
     L.oit_workspace_bytes.restype = SZ
     L.oit_render_fwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.oit_l1_loss.argtypes = [P, P, P, I32, P, P, P, SZ, P]
+    L.oit_l1_loss_workspace_bytes.argtypes = []
+    L.oit_l1_loss_workspace_bytes.restype = SZ
     L.oit_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.oit_select_workspace_bytes.argtypes = [I64]
     L.oit_select_workspace_bytes.restype = SZ
@@ -178,6 +180,10 @@ def l1_loss(image, target, cams_arr, n_views, grad_image, loss, ws, stream=None)
     rc = lib.oit_l1_loss(_ptr(image), _ptr(target), cams_arr, n_views, _ptr(grad_image), _ptr(loss),
                          _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "oit_l1_loss")
+
+
+def l1_loss_workspace_bytes() -> int:
+    return int(lib.oit_l1_loss_workspace_bytes())
 
 
 def loss_workspace_bytes(cams_arr, n_views) -> int:

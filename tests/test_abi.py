@@ -115,3 +115,20 @@ def test_density_entry_points_validate_on_host(lib):
     assert oit.lib.oit_densify_apply(ctypes.byref(sp), six, six, None, six, six, six, 10, fake, 1 << 30, None) == -1
     assert oit.lib.oit_reset_opacity(None, None, None, 10, 0.01, None) == -1
     assert oit.lib.oit_reset_opacity(fake, fake, fake, 10, 1.5, None) == -1
+
+
+def test_l1_loss_workspace_is_the_render_workspace_head(lib):
+    """oit_l1_loss needs a fixed head (status, camera table, its block shares); every
+    render workspace starts with that head, and a smaller buffer is refused on the host."""
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd import scenes
+    need = oit.l1_loss_workspace_bytes()
+    assert need >= 2048 * 8 and need % 256 == 0
+    for w, h, views in ((64, 48, 1), (1600, 1200, 16), (1960, 1090, 8)):
+        cams = oit.camera_array([scenes.look_at_camera((0, 0, -3), w, h)] * views)
+        for tile in (8, 16, 32):
+            assert oit.workspace_bytes(oit.Capacity(100, 100, 0), cams, views, oit.Tuning(tile, 64, 1)) >= need
+    cams = oit.camera_array([scenes.look_at_camera((0, 0, -3), 64, 48)])
+    fake = ctypes.c_void_p(4096)
+    rc = oit.lib.oit_l1_loss(fake, fake, cams, 1, fake, fake, fake, need - 1, None)
+    assert rc == -4 and b"needs" in oit.lib.oit_last_error()

@@ -190,6 +190,79 @@ def test_l1_loss_matches_oracle():
     np.testing.assert_array_equal(to_np(gi).reshape(3, 128, 128), g.astype(np.float32).astype(np.float64))
 
 
+def test_l1_loss_writes_only_its_workspace_head():
+    """The L1 loss given a workspace of exactly oit_l1_loss_workspace_bytes() inside a
+    larger sentinel-filled buffer leaves every byte past that size untouched."""
+    sc = scenes.make_scene(2)
+    cams = oit.camera_array(sc.cameras)
+    need = oit.l1_loss_workspace_bytes()
+    buf = torch.full((need + 256 + 65536,), 0xA5, dtype=torch.uint8, device=DEV)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + need]
+    rng = np.random.default_rng(2)
+    img = torch.tensor(rng.random(3 * 800 * 800).astype(np.float32), device=DEV)
+    tgt = torch.tensor(rng.random(3 * 800 * 800).astype(np.float32), device=DEV)
+    gi = torch.zeros_like(img)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    oit.l1_loss(img, tgt, cams, 1, gi, loss, ws)
+    torch.cuda.synchronize()
+    tail = buf[off + need:]
+    assert bool((tail == 0xA5).all())
+    L, _ = O.l1_loss(to_np(img).reshape(3, 800, 800), to_np(tgt).reshape(3, 800, 800))
+    assert float(loss.item()) == pytest.approx(L, rel=1e-7)
+
+
+def test_l1_loss_on_the_render_workspace_keeps_the_backward_exact():
+    """forward, L1 loss on the renderer's own workspace, backward: the gradients equal
+    the oracle's for the same loss gradient (the loss must not disturb the tile lists
+    and records the backward reads), dense at tile 16 and 5% active at tile 32."""
+    sc = scenes.random_scene(27, 6000, 160, 120, n_views=2, mean_range=1.0)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    for tile, frac in ((16, None), (32, 0.05)):
+        n = sc.n
+        act = pre = None
+        if frac is None:
+            r = Renderer(sc.cameras, n, tile=tile)
+            r.fit_pair_capacity(params, sigma, sc.background)
+            rows = np.arange(n)
+        else:
+            k = int(np.ceil(frac * n))
+            idx, didx, dsg, _ = run_select(torch.rand(n, device=DEV), torch.ones(n, dtype=torch.uint8, device=DEV),
+                                           k)
+            act = {"idx": torch.tensor(idx, dtype=torch.int32, device=DEV),
+                   "n": torch.tensor([len(idx)], dtype=torch.int32, device=DEV),
+                   "delta_idx": torch.tensor(didx, dtype=torch.int32, device=DEV),
+                   "delta_sign": torch.tensor(dsg, dtype=torch.int8, device=DEV),
+                   "n_delta": torch.tensor([len(didx)], dtype=torch.int32, device=DEV)}
+            pre = torch.zeros(9 * r_total_px(sc), device=DEV)
+            r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=len(didx), tile=tile)
+            r.fit_pair_capacity(params, sigma, sc.background, act, pre)
+            rows = idx
+        r.forward(params, sigma, sc.background, act, pre)
+        tgt = r.pack(sc.targets)
+        gi = torch.zeros_like(r.image)
+        loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+        oit.l1_loss(r.image, tgt, r.cams_arr, r.n_views, gi, loss, r.ws)
+        g_gpu = new_grads(r.cap.active_capacity, DEV)
+        gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+        r.backward(params, sigma, sc.background, gi, g_gpu, gsig, act, pre)
+        torch.cuda.synchronize()
+        assert r.status() == 0
+        g_views = [to_np(v) for v in r.views(gi, 3)]
+        g_ref, _ = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras, g_views)
+        ref = {kk: v[:, rows] for kk, v in g_ref.items()}
+        fl = grad_floor(ref)
+        for name, _ in O.GROUPS:
+            rel, _ = grad_rel(to_np(g_gpu[name])[:, :len(rows)], ref[name], fl)
+            log(f"  tile {tile} active {frac}: grad {name} rel {rel:.2e}")
+            assert rel <= GRAD_RTOL, (tile, name, rel)
+
+
+def r_total_px(sc):
+    return sum(c.width * c.height for c in sc.cameras)
+
+
 def test_odd_pixel_counts_take_the_scalar_pixel_kernels():
     """A batch whose first view has an odd pixel count (101 x 77), so that the second
     view's planes start off any 16-byte boundary: L1 loss and gradient, images and
