@@ -483,10 +483,9 @@ def densify_stats(params, sigma, bg, cams, dLdCs, accum=None, denom=None, max_ra
 
 
 def densify_decisions(params, accum, denom, max_radius, uniform, rules: DensityRules):
-    """Per splat: (clone, split, keep_original, keep_clone, keep_children) boolean arrays.
-    These comparisons decide integers (which splats exist), so they are taken in float32,
-    the kernels' precision (the paper fixes none)."""
-    f = np.float32
+    """Per splat: (clone, split, keep_original, keep_clone, keep_children) boolean arrays,
+    every comparison in float64 (the paper fixes no precision for them)."""
+    f = np.float64
     accum, denom = np.asarray(accum, f), np.asarray(denom, f)
     avg = np.where(denom > 0, accum / np.where(denom > 0, denom, f(1)), f(0))
     cand = (avg >= f(rules.grad_threshold)) & (np.asarray(uniform, f) < f(rules.keep_probability))

@@ -138,6 +138,14 @@ def test_keep_probability_extremes_and_count():
     clone, split, ko, kc, kch = O.densify_decisions(p, accum, denom, radius, uniform, RULES)
     _, _, _, src = O.densify(p, zeros, zeros, accum, denom, radius, uniform, normals, RULES)
     assert len(src) == ko.sum() + kc.sum() + 2 * kch.sum()
+    # the draw u ~ U[0, 1) keeps a candidate iff u < p: a draw of exactly 0 with p = 0 and a
+    # draw equal to p are not kept (p = 0 never densifies, p = 1 always does)
+    for prob in (0.0, float(uniform[7])):
+        u = uniform.copy()
+        u[7] = prob
+        r = O.DensityRules(**{**RULES.__dict__, "keep_probability": prob})
+        clone, split, _, _, _ = O.densify_decisions(p, accum, denom, radius, u, r)
+        assert not clone[7] and not split[7]
 
 
 def test_reset_opacity_clamps_and_restarts_moments():

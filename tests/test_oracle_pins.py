@@ -345,6 +345,22 @@ def test_window_equals_full_frame():
     assert np.array_equal(a["image"][:, 5:33, 7:30], b["image"][:, 5:33, 7:30])
 
 
+def test_weight_gradients_are_scale_invariant():
+    """F = P / Q does not change when every weight is scaled by the same factor, and T
+    does not depend on the weights, so per view sum_i w_i dL/dw_i = 0 (Euler's identity
+    for a function homogeneous of degree 0 in w).  This holds for any dL/dC."""
+    sc = tiny_scene(seed=9)
+    F = {f: k for k, f in enumerate(O.PROJECT_FIELDS)}
+    rng = np.random.default_rng(9)
+    cam = sc.cameras[0]
+    g = rng.normal(size=(3, cam.height, cam.width))
+    _, _, scr = O.backward(sc.params, sc.sigma, sc.background, cam, g, screen=True)
+    w = O.project(sc.params, sc.sigma, cam)[:, F["w"]]
+    terms = w * scr[:, 9]
+    assert np.abs(terms).sum() > 0
+    assert abs(terms.sum()) <= 1e-12 * np.abs(terms).sum()
+
+
 def test_permutation_invariance():
     """The composite does not depend on splat order (App. A: no depth order)."""
     sc = tiny_scene()
@@ -492,6 +508,58 @@ def test_topk_matches_lexsort():
         got = O.select_topk(s, k)
         order = np.lexsort((np.arange(len(s)), -s.astype(np.float64)))
         np.testing.assert_array_equal(got, np.sort(order[:k]))
+
+
+def _group_grads(rows):
+    """Zero gradients of every group for ``rows`` listed rows ([C][rows])."""
+    return {g: np.zeros((c, rows)) for g, c in O.GROUPS}
+
+
+def test_activeness_score_hand_values():
+    """Sec. 4.1 Eq. "activeness" with the text after it: a splat is active when at least
+    one attribute group's gradient (L2 norm) is above that group's threshold, so its score
+    is the largest ratio ||grad_g||_2 / eps_g.  Values below are worked out by hand."""
+    g = _group_grads(4)
+    # row 0: only the mean is over its threshold (norm 5 of (3, 4, 0)); every other group
+    # is at a tenth of its threshold.  "At least one" gives 5; "every group" would give 0.1.
+    g["mean"][:, 0] = (3.0, 4.0, 0.0)
+    for name, c in O.GROUPS[1:]:
+        g[name][:, 0] = 0.0
+        g[name][0, 0] = 0.1
+    # row 1: one group, entries whose L2 norm (13), L1 norm (17) and max (12) all differ
+    g["log_scale"][:, 1] = (0.0, 5.0, -12.0)
+    # row 2: every one of the 48 colour-SH entries 0.5: L2 norm sqrt(12)
+    g["sh"][:, 2] = 0.5
+    # row 3: mean norm 3, colour-SH norm 10: the per-group thresholds decide the winner
+    g["mean"][:, 3] = (0.0, 3.0, 0.0)
+    g["sh"][7, 3] = -10.0
+    s = O.activeness_score(g, np.arange(4))
+    np.testing.assert_allclose(s, [5.0, 13.0, math.sqrt(12.0), 10.0], rtol=1e-15)
+    eps = {name: 1.0 for name, _ in O.GROUPS}
+    eps["sh"] = 100.0          # sh at 0.1 of its threshold: the mean's 3 wins
+    eps["log_scale"] = 26.0
+    s = O.activeness_score(g, np.arange(4), eps)
+    np.testing.assert_allclose(s, [5.0, 0.5, math.sqrt(12.0) / 100.0, 3.0], rtol=1e-15)
+    # a splat with no gradient at all scores 0
+    assert O.activeness_score(_group_grads(1), np.arange(1))[0] == 0.0
+
+
+def test_select_threshold_is_strict():
+    """The active set is the splats whose score is strictly above the threshold: a norm
+    exactly at its threshold does not make a splat active (Sec. 4.1)."""
+    s = np.array([0.5, 1.0, np.nextafter(1.0, 2.0), 2.0, 1.0, 0.0])
+    np.testing.assert_array_equal(O.select_threshold(s, 1.0), [2, 3])
+    np.testing.assert_array_equal(O.select_threshold(s, 0.0), [0, 1, 2, 3, 4])
+    assert len(O.select_threshold(s, 2.0)) == 0
+    # the two together: a group exactly at its threshold and nothing above it -> inactive
+    g = _group_grads(2)
+    g["opacity_logit"][0, 0] = 0.25
+    g["vsh"][:4, 1] = 0.5       # norm 1.0
+    eps = {name: 1.0 for name, _ in O.GROUPS}
+    eps["opacity_logit"] = 0.25
+    sc = O.activeness_score(g, np.arange(2), eps)
+    np.testing.assert_array_equal(sc, [1.0, 1.0])
+    assert len(O.select_threshold(sc, 1.0)) == 0
 
 
 def test_label_delta():
