@@ -395,7 +395,8 @@ oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_st
  * Wait for `stream` and copy the counters the last oit_render_fwd / oit_render_bwd on
  * this workspace left (arguments as given to that call; out (host) [5]):
  *   out[0] (tile, splat) entries the forward needed (also when it overflowed
- *          tuning.pair_capacity, so a caller can size pair_capacity and run again),
+ *          tuning.pair_capacity, so a caller can size pair_capacity and run again;
+ *          saturated at 2^32 - 1, above any pair capacity),
  *   out[1] contributing (alpha >= 1/255) active (splat, pixel) pairs it blended,
  *   out[2] active (splat, pixel) pairs it evaluated (tile entries x in-image tile pixels),
  *   out[3] backward work items (up to 64 active entries of one tile each),

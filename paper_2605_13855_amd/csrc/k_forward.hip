@@ -425,8 +425,49 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, int64_t 
 }
 
 // the same scan for a count that lives on the device: a fixed grid of kScanGrid blocks,
-// each scanning a contiguous range of whole kScanBlockItems tiles
-constexpr unsigned kScanGrid = 1024;
+// each scanning a contiguous range of whole kScanBlockItems tiles.  The sums are formed
+// in 64 bits and stored saturated at 2^32 - 1: a prefix at or past that value is past
+// every pair capacity (which is below 2^32 - 1), so its entries are dropped and the
+// overflow is reported instead of the offsets wrapping round.
+constexpr unsigned kScanGrid = kScanThreads;   // the workspace holds this many block sums
+constexpr uint64_t kSat32 = 0xffffffffull;
+
+__device__ __forceinline__ uint32_t sat32(uint64_t x) { return (uint32_t)(x < kSat32 ? x : kSat32); }
+
+__device__ __forceinline__ uint64_t block_excl_scan256_u64(uint64_t v, uint64_t *total)
+{
+    __shared__ uint64_t s_w[256];
+    s_w[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint64_t t = threadIdx.x >= (unsigned)off ? s_w[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        s_w[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const uint64_t incl = s_w[threadIdx.x];
+    if (total) *total = s_w[255];
+    __syncthreads();
+    return incl - v;
+}
+
+// exclusive scan of the kScanGrid block sums in place, saturated (one block)
+__global__ __launch_bounds__(kScanThreads) void k_scan_block_sums_sat(uint32_t *bsum)
+{
+    __shared__ uint64_t s_v[kScanThreads];
+    static_assert(kScanGrid == kScanThreads, "one block sum per thread");
+    const int tid = threadIdx.x;
+    const uint64_t x = bsum[tid];
+    s_v[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const uint64_t t = tid >= off ? s_v[tid - off] : 0ull;
+        __syncthreads();
+        s_v[tid] += t;
+        __syncthreads();
+    }
+    bsum[tid] = sat32(s_v[tid] - x);
+}
 
 __device__ __forceinline__ void scan_range(uint64_t n, uint64_t &lo, uint64_t &hi)
 {
@@ -441,11 +482,11 @@ __global__ __launch_bounds__(256) void k_scan_sums_dev(const uint32_t *in, const
 {
     uint64_t lo, hi;
     scan_range(*nptr, lo, hi);
-    uint32_t acc = 0;
+    uint64_t acc = 0;
     for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) acc += in[i];
-    uint32_t tot = 0;
-    block_excl_scan256(acc, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    uint64_t tot = 0;
+    block_excl_scan256_u64(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sat32(tot);
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply_dev(const uint32_t *in, const uint32_t *nptr,
@@ -453,31 +494,32 @@ __global__ __launch_bounds__(256) void k_scan_apply_dev(const uint32_t *in, cons
 {
     uint64_t lo, hi;
     scan_range(*nptr, lo, hi);
-    uint32_t carry = bsum[blockIdx.x];
+    uint64_t carry = bsum[blockIdx.x];
     for (uint64_t base = lo; base < hi; base += kScanBlockItems) {
         const uint64_t t0 = base + (uint64_t)threadIdx.x * kScanPer;
         uint32_t v[kScanPer];
-        uint32_t acc = 0;
+        uint64_t acc = 0;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             v[k] = t0 + k < hi ? in[t0 + k] : 0u;
             acc += v[k];
         }
-        uint32_t tot = 0;
-        uint32_t pre = block_excl_scan256(acc, &tot) + carry;
+        uint64_t tot = 0;
+        uint64_t pre = block_excl_scan256_u64(acc, &tot) + carry;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            if (t0 + k < hi) out[t0 + k] = pre;
+            if (t0 + k < hi) out[t0 + k] = sat32(pre);
             pre += v[k];
         }
         carry += tot;
     }
 }
 
+// exclusive scan of n (device count) uint32 values, saturated at 2^32 - 1
 void launch_scan_u32_dev(const uint32_t *in, uint32_t *out, const uint32_t *nptr, uint32_t *tmp, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scan_sums_dev, dim3(kScanGrid), dim3(256), 0, s, in, nptr, tmp);
-    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, (int64_t)kScanGrid);
+    hipLaunchKernelGGL(k_scan_block_sums_sat, dim3(1), dim3(kScanThreads), 0, s, tmp);
     hipLaunchKernelGGL(k_scan_apply_dev, dim3(kScanGrid), dim3(256), 0, s, in, nptr, (const uint32_t *)tmp, out);
 }
 
@@ -511,7 +553,8 @@ __global__ void k_pair_count(ListArgs a)
     a.b.counters[CNT_NPAIRS] = (uint32_t)it.total;
 }
 
-// total tile entries E, the sorted list's length min(E, capacity), overflow status
+// total tile entries E (saturated at 2^32 - 1: the scan saturates), the sorted list's
+// length min(E, capacity), overflow status
 __global__ void k_list_total(ListArgs a)
 {
     const uint32_t np = a.b.counters[CNT_NPAIRS];

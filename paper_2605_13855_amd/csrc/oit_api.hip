@@ -183,8 +183,12 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     const size_t npairs = (size_t)n_views * p.Rcap;
     p.nhits = o; o = align256(o + 4 * npairs);
     p.hoff = o; o = align256(o + 4 * npairs);
+    // block sums of the scans: the host-sized scan of the radix histograms, and the
+    // device-count scan of the pairs' tile counts, which always uses kScanThreads blocks
     const size_t nscan = npairs > kRadixBuckets * (size_t)kSortGrid ? npairs : kRadixBuckets * (size_t)kSortGrid;
-    p.scan_tmp = o; o = align256(o + 4 * (nscan / kScanBlockItems + 2));
+    const size_t nsums = nscan / kScanBlockItems + 2 > (size_t)kScanThreads ? nscan / kScanBlockItems + 2
+                                                                             : (size_t)kScanThreads;
+    p.scan_tmp = o; o = align256(o + 4 * nsums);
     p.ep = o; o = align256(o + 4 * kEpStride * pc);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
     p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);

@@ -132,3 +132,17 @@ def test_l1_loss_workspace_is_the_render_workspace_head(lib):
     fake = ctypes.c_void_p(4096)
     rc = oit.lib.oit_l1_loss(fake, fake, cams, 1, fake, fake, fake, need - 1, None)
     assert rc == -4 and b"needs" in oit.lib.oit_last_error()
+
+
+def test_pair_capacity_bound_on_the_host(lib):
+    """Tile-entry offsets are 32-bit: the host refuses a pair capacity of 2^32 - 1 or more,
+    so every offset at or past the capacity (the device scan saturates there) is dropped
+    and reported as an overflow instead of wrapping round."""
+    from paper_2605_13855_amd import oit
+    from paper_2605_13855_amd import scenes
+    cams = oit.camera_array([scenes.look_at_camera((0, 0, -3), 64, 48)])
+    cap = oit.Capacity(100, 100, 0)
+    assert oit.workspace_bytes(cap, cams, 1, oit.Tuning(16, 64, 2 ** 32 - 2)) > 4 * (2 ** 32 - 2)
+    assert oit.workspace_bytes(cap, cams, 1, oit.Tuning(16, 64, 2 ** 32 - 1)) == 0
+    assert b"pair_capacity" in oit.lib.oit_last_error()
+    assert oit.workspace_bytes(cap, cams, 1, oit.Tuning(16, 64, 0)) == 0

@@ -534,6 +534,32 @@ def test_pair_overflow_is_reported_and_bounded():
     assert r.status() == 0
 
 
+def test_entry_count_past_32_bits_is_reported_not_wrapped():
+    """20,000 splats that each cover a whole 4096 x 4096 view at tile 8 need 5.2e9 tile
+    entries, more than 32-bit offsets hold: the count saturates at 2^32 - 1, the overflow
+    bit is set and the call stays within its capacity."""
+    n = 20000
+    rng = np.random.default_rng(61)
+    cam = scenes.look_at_camera((0.0, 0.0, -3.0), 4096, 4096)
+    p = {g: np.zeros((c, n)) for g, c in O.GROUPS}
+    p["mean"][:] = rng.uniform(-0.05, 0.05, size=(3, n))
+    p["log_scale"][:] = 0.3
+    p["quat"][0] = 1.0
+    p["opacity_logit"][:] = 4.0
+    p["vsh"][0] = 1.0
+    params = params_to_device(p)
+    sigma = torch.tensor([10.0], device=DEV)
+    r = Renderer([cam], n, tile=8, batch=64, pair_capacity=1 << 20)
+    r.forward(params, sigma, (0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    st = r.status()
+    need = r.pairs_needed()
+    log(f"  status {st}, entries needed (saturated) {need}")
+    assert st & oit.STATUS_PAIR_OVERFLOW
+    assert need == 2 ** 32 - 1
+    assert bool(torch.isfinite(r.image).all())
+
+
 def test_forward_and_backward_are_run_to_run_reproducible():
     """The tile lists come from a stable sort, the backward has no atomics and dL/dsigma
     adds its block shares in a fixed order: two calls on the same inputs give bitwise
