@@ -27,11 +27,12 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, 256 CUs x 2.4 GHz x 256 flop
 PEAK_HBM_GBS = 8000.0
 # algorithmic flops per (splat, pixel) pair, an FMA counting 2.  Evaluated pair: the
 # exponent's column and row terms and the threshold test.  Forward, contributing: exp,
-# cap, alpha w, three P FMAs, the Q add, the T update.  Backward, contributing: A.c - s1,
-# three dL/dc FMAs, dL/dw, dL/dalpha = B / (1 - alpha) + w (A.c - s1), dL/de, the six
+# cap, alpha w, three P FMAs, the Q add, the dQ/dsigma FMA, the T update.  Backward,
+# contributing: A.c - s1, three dL/dc FMAs, dL/dw and its lambda-weighted sum (for
+# dL/dsigma), dL/dalpha = B / (1 - alpha) + w (A.c - s1), dL/de, the six
 # exponent-gradient FMAs and dL/dmean'.
-FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 10, 12
-BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 10, 39
+FWD_FLOP_EVAL, FWD_FLOP_CONTRIB = 10, 14
+BWD_FLOP_EVAL, BWD_FLOP_CONTRIB = 10, 41
 
 
 KERNEL_SOURCES = {

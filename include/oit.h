@@ -28,7 +28,8 @@
  *     components is a [C][stride] array whose column r is active row r.
  *   - Per-view images are planar float32.  A batch of V views is packed view after
  *     view: view k starts at plane offset P * pix_base(k), pix_base(k) = sum_{j<k} H_j W_j,
- *     and holds P planes of H_k x W_k (P = 3 for images, 5 for pixstate, 9 for pre).
+ *     and holds P planes of H_k x W_k (P = 3 for images, OIT_PIXSTATE_PLANES = 6 for
+ *     pixstate, 9 for pre).
  *   - Pixel (x, y) has its centre at (x + 0.5, y + 0.5); cameras are pinhole, OpenCV
  *     axes (+x right, +y down, +z forward), x_cam = R x_world + t.
  *   - The caller owns all memory (inputs, outputs and the workspace).  The library
@@ -54,6 +55,9 @@ extern "C" {
 #endif
 
 typedef struct ihipStream_t *oit_stream; /* a hipStream_t */
+
+/* planes per pixel of the forward pass's state (T, Q, F rgb, dQ/dsigma) */
+#define OIT_PIXSTATE_PLANES 6
 
 typedef enum {
     OIT_OK = 0,
@@ -149,12 +153,18 @@ size_t oit_workspace_bytes(const oit_capacity *cap, const oit_camera *cams, int3
  *             was added with, although the splat may have been trained since it became
  *             active: pass the parameters as they were when the labels changed.
  * pre         [V][9][H][W] per-pixel accumulators of the inactive set: P0 (rgb),
- *             P1 (rgb), Q0, Q1, logT with P0 = sum c alpha v, P1 = sum c alpha v d,
- *             Q0 = sum alpha v, Q1 = sum alpha v d over inactive splats with d < sigma,
- *             logT = sum log(1 - alpha) over all inactive splats; updated in place by
- *             the label changes.  NULL in dense mode.
+ *             P1 (rgb), Q0, Q1, logT with P0 = sum (c - 1/2) alpha v,
+ *             P1 = sum (c - 1/2) alpha v d, Q0 = sum alpha v, Q1 = sum alpha v d over
+ *             inactive splats with d < sigma, logT = sum log(1 - alpha) over all
+ *             inactive splats; updated in place by the label changes.  The colour
+ *             sums are centred on the colour offset 1/2 so that they hold both signs:
+ *             their float rounding then stays small against the differences that
+ *             d/dsigma forms of them.  A zero buffer is the empty set.  NULL in dense
+ *             mode.
  * image       [V][3][H][W] output C
- * pixstate    [V][5][H][W] output T, Q, F (rgb): what the backward pass needs
+ * pixstate    [V][6][H][W] output T, Q, F (rgb), dQ/dsigma = sum alpha v d / sigma^2 over
+ *             the contributing splats with d < sigma (active and pre): what the
+ *             backward pass needs
  * ws          workspace of oit_workspace_bytes(...) bytes, 256-byte aligned
  */
 oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const float *bg,
@@ -209,7 +219,11 @@ oit_status oit_l1_dssim_loss(const float *image, const float *target, const oit_
  * projection): given dL/dC for every view, write the gradient of every parameter of
  * the active rows and of sigma.  Each splat's gradient is independent of the others
  * (App. B), so the kernel runs one splat per lane over its tile's pixels.
- * The inactive splats' share of d/dsigma comes from pre (P1, Q1).
+ * The inactive splats' share of d/dsigma comes from pre.  d/dsigma is formed as
+ * sum over pixels and splats of dL/dw_i (dw_i/dsigma - lambda w_i) with
+ * lambda = (dQ/dsigma) / Q per pixel; the lambda term is zero in exact arithmetic
+ * (sum_i alpha_i w_i (c_i - F) = 0 at every pixel) and removes the first-order effect
+ * of the float rounding of F on d/dsigma.
  *
  * grad_image  [V][3][H][W] dL/dC
  * pixstate    the forward pass's output

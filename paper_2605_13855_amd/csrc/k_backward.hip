@@ -119,11 +119,24 @@ void launch_l1_loss(const Buffers &b, const float *image, const float *target, f
 // ---------------------------------------------------------------------------------
 // per-pixel constants of the partials:
 //   A_ch = g_ch (1 - T) / Q   (0 if Q <= 0),  s1 = sum_ch A_ch F_ch,
-//   B    = T sum_ch g_ch (F_ch - c0_ch)
+//   B    = T sum_ch g_ch (F_ch - c0_ch),  lambda = (dQ/dsigma) / Q  (0 if Q <= 0)
 // so that for a contributing pair  dL/dc = A alpha w,  dL/dw = alpha (A.c - s1),
 //   dL/dalpha = B / (1 - alpha) + w (A.c - s1).
-// The inactive set's share of dL/dsigma, sum_ch A_ch (P1_ch - F_ch Q1) / sigma^2, is
-// summed here from the pre-rendered accumulators.
+//
+// dL/dsigma.  F is the alpha w weighted mean of the colours, so at every pixel
+// sum_i alpha_i w_i (c_i - F) = 0 exactly.  Hence
+//   dL/dsigma = sum_p sum_i A . (c_i - F) alpha_i (dw_i/dsigma - lambda_p w_i)
+// for any per-pixel lambda_p, and lambda_p = (dQ/dsigma) / Q (dQ/dsigma = sum_i alpha_i
+// dw_i/dsigma) makes the sum insensitive, to first order, to an error in F: an error
+// dF moves it by -A.dF sum_i alpha_i (dw_i/dsigma - lambda_p w_i) = 0.  Without the
+// lambda term the float32 rounding of the forward's sums P and Q over ~10^3 splats
+// per pixel enters dL/dsigma amplified by its cancellation (Sec. 1 Eq. "sf_weight";
+// App. B, the dC/dw term).  Each splat therefore also sums lambda alpha (A.c - s1).
+// The inactive set's share, sum_ch A_ch [(P1_ch - F_ch Q1) / sigma^2
+//   - lambda (P0_ch - P1_ch / sigma - F_ch (Q0 - Q1 / sigma))]
+//   = sum_ch A_ch [u P1'_ch - lambda P0'_ch + (1/2 - F_ch) (u Q1 - lambda Q0)],
+// u = 1 / sigma^2 + lambda / sigma, is summed here from the pre-rendered accumulators,
+// whose colour sums P0', P1' are stored centred on the colour offset 1/2.
 // ---------------------------------------------------------------------------------
 struct PixArgs {
     Buffers b;
@@ -142,39 +155,43 @@ __global__ __launch_bounds__(256) void k_pixconst(PixArgs a)
     const float *__restrict__ grad = a.grad;
     const float *__restrict__ pre = a.pre;
     float4 *__restrict__ pixconst = a.b.pixconst;
-    float *__restrict__ pixB = a.b.pixB;
+    float2 *__restrict__ pixB = a.b.pixB;
+    const double sig = (double)*a.sigma, isig = 1.0 / sig, isig2 = isig * isig;
     for_batch_pixels(a.b, [&](size_t pb, size_t HW, size_t local) {
-        const float *ps = pixstate + 5 * pb + local;
+        const float *ps = pixstate + kPixStatePlanes * pb + local;
         const float *gr = grad + 3 * pb + local;
-        const float T = ps[0], Q = ps[HW];
+        const float T = ps[0], Q = ps[HW], Qs = ps[5 * HW];
         const float F[3] = {ps[2 * HW], ps[3 * HW], ps[4 * HW]};
         const float g[3] = {gr[0], gr[HW], gr[2 * HW]};
-        float P1[3] = {0.f, 0.f, 0.f}, Q1 = 0.f;
+        float P0[3] = {0.f, 0.f, 0.f}, P1[3] = {0.f, 0.f, 0.f}, Q0 = 0.f, Q1 = 0.f;
         if constexpr (PRE) {
             const float *pr = pre + 9 * pb + local;
-            P1[0] = pr[3 * HW];
-            P1[1] = pr[4 * HW];
-            P1[2] = pr[5 * HW];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                P0[ch] = pr[ch * HW];
+                P1[ch] = pr[(3 + ch) * HW];
+            }
+            Q0 = pr[6 * HW];
             Q1 = pr[7 * HW];
         }
         const float k = Q > 0.f ? (1.f - T) / Q : 0.f;
+        const float lam = Q > 0.f ? Qs / Q : 0.f;
         const float A0 = g[0] * k, A1 = g[1] * k, A2 = g[2] * k;
         const float s1 = A0 * F[0] + A1 * F[1] + A2 * F[2];
         const float B = T * (g[0] * (F[0] - a.bg0) + g[1] * (F[1] - a.bg1) + g[2] * (F[2] - a.bg2));
         pixconst[pb + local] = make_float4(A0, A1, A2, -s1);
-        pixB[pb + local] = B;
+        pixB[pb + local] = make_float2(B, lam);
         if constexpr (PRE) {
-            // numerator of sum_ch A_ch (P1_ch - F_ch Q1) / sigma^2; divided once below
-            acc += (double)A0 * ((double)P1[0] - (double)F[0] * Q1) +
-                   (double)A1 * ((double)P1[1] - (double)F[1] * Q1) +
-                   (double)A2 * ((double)P1[2] - (double)F[2] * Q1);
+            const double A[3] = {A0, A1, A2};
+            const double ld = (double)lam, u = isig2 + ld * isig;
+            const double qt = u * (double)Q1 - ld * (double)Q0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                acc += A[ch] * (u * (double)P1[ch] - ld * (double)P0[ch] + ((double)kColorOffset - (double)F[ch]) * qt);
         }
     });
     const double t = block_sum_double(acc);
-    if (threadIdx.x == 0) {
-        const double sig = (double)*a.sigma;
-        a.b.sig_part[blockIdx.x] = PRE ? t / (sig * sig) : 0.0;
-    }
+    if (threadIdx.x == 0) a.b.sig_part[blockIdx.x] = PRE ? t : 0.0;
 }
 
 void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], const float *pre,
@@ -209,7 +226,8 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // serialise at the memory side, so no wave polls the other XCDs' queues.
 //
 // Screen-space gradient layout (10 floats): d/dmx, d/dmy, d/dqa, d/dqb, d/dqc, d/dlo,
-// d/dc (rgb), d/dw -- q* and lo as in the record.
+// d/dc (rgb), d/dw, and sum lambda alpha (A.c - s1) for dL/dsigma -- q* and lo as in
+// the record.
 // ---------------------------------------------------------------------------------
 struct BwdArgs {
     Buffers b;
@@ -228,8 +246,9 @@ __global__ __launch_bounds__(256) void k_chunk_map(Buffers b)
 
 // Per-lane sums of the backward over the pixels of its tile entry.  g_c* hold
 // sum A_ch alpha; dL/dc_ch = w times that (w is the lane's), taken once at the end.
+// g_w = dL/dw; g_h = the same sum weighted by the pixel's lambda (for dL/dsigma).
 struct BwdSums {
-    float g_cr, g_cg, g_cb, g_w;
+    float g_cr, g_cg, g_cb, g_w, g_h;
     // moments of dL/de (without the ln 2 of d alpha / de) over the pixel offsets
     float m0, m_x, m_y, m_xx, m_xy, m_yy;
 };
@@ -239,7 +258,7 @@ struct BwdSums {
 // derivative cut where it is; otherwise every alpha stays below 0.99 (the splats'
 // opacities are below it with a margin) and neither step is needed.
 template <bool CAP>
-__device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, int gxp, int gyp, float dx0, float dy0,
+__device__ __forceinline__ void bwd_group(const float4 *pcs, const float2 *pBs, int gxp, int gyp, float dx0, float dy0,
                                           float qa, float qb, float qc, float lo, float cr, float cg, float cb,
                                           float w, BwdSums &o)
 {
@@ -258,7 +277,7 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, i
             const float e = exp_pix(qc, dy[r], kb, kc);
             if (e >= kLog2AlphaMin) {
                 const float4 pc = pcs[r * kGroup + c];
-                const float Bc = pBs[r * kGroup + c];
+                const float2 Bl = pBs[r * kGroup + c];
                 const float ex = __builtin_amdgcn_exp2f(e);
                 const float al = CAP ? fminf(ex, kAlphaMax) : ex;
                 // A . c - s1 (pc.w holds -s1)
@@ -266,9 +285,11 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float *pBs, i
                 o.g_cr = fmaf(pc.x, al, o.g_cr);
                 o.g_cg = fmaf(pc.y, al, o.g_cg);
                 o.g_cb = fmaf(pc.z, al, o.g_cb);
-                o.g_w = fmaf(al, diff, o.g_w);
+                const float ad = al * diff;
+                o.g_w += ad;
+                o.g_h = fmaf(ad, Bl.y, o.g_h);
                 // dL/de / ln 2 = alpha (B / (1 - alpha) + w diff); zero where alpha is capped
-                const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                const float dLda = fmaf(w, diff, Bl.x * __builtin_amdgcn_rcpf(1.f - al));
                 const float dLde = (CAP ? (al < kAlphaMax ? al : 0.f) : al) * dLda;
                 c0 += dLde;
                 const float ey = dLde * dy[r];
@@ -299,13 +320,13 @@ __device__ __forceinline__ void write_partials(float *dst, float qa, float qb, f
     ((float4 *)dst)[0] = make_float4(-(2.f * qa * o.m_x + qb * o.m_y) * kLn2, -(qb * o.m_x + 2.f * qc * o.m_y) * kLn2,
                                      o.m_xx * kLn2, o.m_xy * kLn2);
     ((float4 *)dst)[1] = make_float4(o.m_yy * kLn2, o.m0 * kLn2, w * o.g_cr, w * o.g_cg);
-    ((float2 *)dst)[4] = make_float2(w * o.g_cb, o.g_w);
+    ((float4 *)dst)[2] = make_float4(w * o.g_cb, o.g_w, o.g_h, 0.f);
 }
 
 template <int S>
 // boxed: the wave's count of items walked box by box (for the counters)
 __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
-                                         float4 (*s_c)[64], float (*s_B)[64], uint32_t &boxed)
+                                         float4 (*s_c)[64], float2 (*s_B)[64], uint32_t &boxed)
 {
     constexpr int GX = S / kGroup;   // groups per tile edge
     const uint64_t cap = (uint64_t)b.pair_cap;
@@ -361,7 +382,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         if (valid) {
             ((float4 *)dst)[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             ((float4 *)dst)[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            ((float2 *)dst)[4] = make_float2(0.f, 0.f);
+            ((float4 *)dst)[2] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         return;
     }
@@ -387,12 +408,12 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         for (int m = 32; m > 0; m >>= 1) amax = max(amax, __shfl_xor(amax, m));
         if (amax <= kBoxPerGroup * __builtin_popcount(mask)) {
             ++boxed;
-            BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             int c = bc0, r = br0;
             // the constants of the lane's next box pixel are fetched one pixel ahead
             const size_t row0 = pb + (size_t)(ty * S) * cam.W + (size_t)(tx * S);
             float4 npc = make_float4(0.f, 0.f, 0.f, 0.f);
-            float nBc = 0.f;
+            float2 nBc = make_float2(0.f, 0.f);
             if (area > 0) {
                 npc = b.pixconst[row0 + (size_t)r * cam.W + c];
                 nBc = b.pixB[row0 + (size_t)r * cam.W + c];
@@ -400,7 +421,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
             for (int k = 0; k < amax; ++k) {
                 if (k < area) {
                     const float4 pc = npc;
-                    const float Bc = nBc;
+                    const float2 Bl = nBc;
                     const float dx = dx0 + (float)c, dy = dy0 + (float)r;
                     if (++c > bc1) {
                         c = bc0;
@@ -418,8 +439,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
                         o.g_cr = fmaf(pc.x, al, o.g_cr);
                         o.g_cg = fmaf(pc.y, al, o.g_cg);
                         o.g_cb = fmaf(pc.z, al, o.g_cb);
-                        o.g_w = fmaf(al, diff, o.g_w);
-                        const float dLda = fmaf(w, diff, Bc * __builtin_amdgcn_rcpf(1.f - al));
+                        const float ad = al * diff;
+                        o.g_w += ad;
+                        o.g_h = fmaf(ad, Bl.y, o.g_h);
+                        const float dLda = fmaf(w, diff, Bl.x * __builtin_amdgcn_rcpf(1.f - al));
                         const float dLde = (al < kAlphaMax ? al : 0.f) * dLda;
                         const float exx = dLde * dx, eyy = dLde * dy;
                         o.m0 += dLde;
@@ -438,10 +461,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
 
     // this lane's pixel when staging a group's constants
     const int sx = lane % kGroup, sy = lane / kGroup;
-    auto fetch = [&](int g, float4 &c, float &Bv) {
+    auto fetch = [&](int g, float4 &c, float2 &Bv) {
         const int x = tx * S + (g % GX) * kGroup + sx, y = ty * S + (g / GX) * kGroup + sy;
         c = make_float4(0.f, 0.f, 0.f, 0.f);
-        Bv = 0.f;
+        Bv = make_float2(0.f, 0.f);
         if (x < cam.W && y < cam.H) {
             const size_t gp = pb + (size_t)y * cam.W + x;
             c = b.pixconst[gp];
@@ -449,11 +472,11 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
     };
 
-    BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int g = __builtin_ctz(mask);
     mask &= mask - 1;
     float4 nc;
-    float nB;
+    float2 nB;
     fetch(g, nc, nB);
     for (;;) {
         s_c[wave][lane] = nc;
@@ -483,7 +506,7 @@ template <int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_bwd(BwdArgs a)
 {
     __shared__ float4 s_c[4][64];
-    __shared__ float s_B[4][64];
+    __shared__ float2 s_B[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
     if (total > a.b.max_chunks) total = a.b.max_chunks;
@@ -537,7 +560,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
     const int col = threadIdx.x % S, row0 = threadIdx.x / S;
     const float colf = (float)col;
-    float rowf[PPT], A0[PPT], A1[PPT], A2[PPT], ns1[PPT], Bc[PPT];
+    float rowf[PPT], A0[PPT], A1[PPT], A2[PPT], ns1[PPT], Bc[PPT], Lc[PPT];
     bool in[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -545,7 +568,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
         rowf[p] = (float)(row0 + p * RSTEP);
         in[p] = x < cam.W && y < cam.H;
         float4 c0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float cB = 0.f;
+        float2 cB = make_float2(0.f, 0.f);
         if (in[p]) {
             const size_t gp = (size_t)cam.pix_base + (size_t)y * cam.W + x;
             c0 = a.b.pixconst[gp];
@@ -555,7 +578,8 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
         A1[p] = c0.y;
         A2[p] = c0.z;
         ns1[p] = c0.w;
-        Bc[p] = cB;
+        Bc[p] = cB.x;
+        Lc[p] = cB.y;
     }
     const uint64_t cap = (uint64_t)a.b.pair_cap;
     const uint64_t off = a.b.tile_off[tile];
@@ -596,6 +620,7 @@ __global__ __launch_bounds__(S * S < 256 ? S * S : 256) void k_raster_bwd_pixel(
                 unsafeAtomicAdd(dst + 7, A1[p] * aw);
                 unsafeAtomicAdd(dst + 8, A2[p] * aw);
                 unsafeAtomicAdd(dst + 9, al * diff);
+                unsafeAtomicAdd(dst + 10, Lc[p] * (al * diff));
                 if (al < kAlphaMax) {
                     const float dLde = fmaf(w, diff, Bc[p] * __builtin_amdgcn_rcpf(1.f - al)) * al * kLn2;
                     const float ex = dLde * dx, ey = dLde * dy;
@@ -704,9 +729,9 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
     o.gsig = 0.0;
 
     // screen-space partials of this (record, view): the sum of its tile entries' rows
-    float gs[10];
+    float gs[kEpUsed];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) gs[k] = 0.f;
+    for (int k = 0; k < kEpUsed; ++k) gs[k] = 0.f;
     {
         // the pair's entries hold the contiguous slots [hoff, hoff + nhits); active rows
         // are the first listed records, so the pair index is view * nrec + t
@@ -716,15 +741,14 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
         const uint64_t n = g0 >= cap ? 0 : (nh < cap - g0 ? nh : cap - g0);
         // rows four at a time: the loads are issued together, the sums stay in row order
         for (uint64_t k = 0; k < n; k += 4) {
-            float4 e0[4], e1[4];
-            float2 e2[4];
+            float4 e0[4], e1[4], e2[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (k + j < n) {
                     const float *e = a.b.ep + (g0 + k + j) * kEpStride;
                     e0[j] = ((const float4 *)e)[0];
                     e1[j] = ((const float4 *)e)[1];
-                    e2[j] = ((const float2 *)e)[4];
+                    e2[j] = ((const float4 *)e)[2];
                 }
             }
 #pragma unroll
@@ -740,13 +764,14 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
                     gs[7] += e1[j].w;
                     gs[8] += e2[j].x;
                     gs[9] += e2[j].y;
+                    gs[10] += e2[j].z;
                 }
             }
         }
     }
     bool any = false;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) any |= gs[k] != 0.f;
+    for (int k = 0; k < kEpUsed; ++k) any |= gs[k] != 0.f;
     if (!any) return;
     const CamDev &cam = a.b.cams[v];
     Geo g;
@@ -785,7 +810,9 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
         if (tz < sigma) {
             const float gv = gw * (1.f - tz / sigma);
             g_tc[2] += -gw * vv / sigma;
-            o.gsig = (double)gw * (double)vv * (double)tz / ((double)sigma * (double)sigma);
+            // sum over the pixels of alpha (A.c - s1) (dw/dsigma - lambda w)
+            const double sd = (double)sigma, vd = (double)vv, zd = (double)tz;
+            o.gsig = (double)gw * vd * zd / (sd * sd) - (double)gs[10] * vd * (1.0 - zd / sd);
             if (raw > 0.f) {
                 o.gvm = gv;
 #pragma unroll

@@ -195,8 +195,10 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
         const float h = -0.5f * kLog2e;
         r.a = make_float4(g.mx, g.my, h * g.con_a, 2.f * h * g.con_b);
         r.b = make_float4(h * g.con_c, lo, col[0], col[1]);
+        // an active record carries dw/dsigma = v d / sigma^2 (0 where d >= sigma) for
+        // the pixel sum dQ/dsigma of the forward pass
         if (sign == 0)
-            r.c = make_float4(col[2], w, 0.f, 1.f);
+            r.c = make_float4(col[2], w, w_on ? vv * d / (sigma * sigma) : 0.f, 1.f);
         else
             r.c = make_float4(col[2], w_on ? vv : 0.f, d, (float)sign);
 
@@ -902,12 +904,14 @@ __device__ __forceinline__ void fold_log_t(float (&dL)[PPT], float (&Tp)[PPT], f
     }
 }
 
-// Blend one active record into a thread's PPT pixels (BAN accumulators).
+// Blend one active record into a thread's PPT pixels (BAN accumulators, and Qs =
+// dQ/dsigma, which the backward pass uses to take dL/dsigma in a form that the float
+// rounding of F does not disturb).
 template <int PPT>
 __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb, const float4 &rc, float cb,
                                              float cc, const float (&rowf)[PPT], const uint64_t (&inmask)[PPT],
                                              unsigned long long &npair, float (&P)[PPT][3], float (&Q)[PPT],
-                                             float (&T)[PPT])
+                                             float (&Qs)[PPT], float (&T)[PPT])
 {
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -921,6 +925,7 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
             P[p][1] = fmaf(rb.w, aw, P[p][1]);
             P[p][2] = fmaf(rc.x, aw, P[p][2]);
             Q[p] += aw;
+            Qs[p] = fmaf(al, rc.z, Qs[p]);
             T[p] *= 1.f - al;
         }
     }
@@ -991,19 +996,25 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
     // Q0 - Q1 / sigma and T = exp(log T); with BAU read here, once the label changes
     // are added, without it read after the active entries
     float preP[PPT][3], preQ[PPT], preT[PPT];
+    // dQ/dsigma at each pixel: Q1 / sigma^2 of the inactive set (added when the stored
+    // terms are read) plus alpha dw/dsigma of the active entries
+    float Qs[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         preP[p][0] = preP[p][1] = preP[p][2] = 0.f;
         preQ[p] = 0.f;
         preT[p] = 1.f;
+        Qs[p] = 0.f;
     }
 
-    // the pixel's stored accumulators -> its inactive-set terms of the composite
+    // the pixel's stored accumulators -> its inactive-set terms of the composite (the
+    // colour sums are stored centred on the colour offset: P = P0 - P1 / sigma + Q / 2)
     auto keep_pre = [&](int p, const float (&pv)[9]) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) preP[p][ch] = pv[ch] - pv[3 + ch] * isig;
         preQ[p] = pv[6] - pv[7] * isig;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) preP[p][ch] = fmaf(kColorOffset, preQ[p], pv[ch] - pv[3 + ch] * isig);
         preT[p] = expf(pv[8]);
+        Qs[p] = fmaf(pv[7], isig * isig, Qs[p]);
     };
     // label changes: BAU accumulators (sign-weighted, sigma-free), added to the
     // pre-rendered buffer
@@ -1030,9 +1041,19 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
         float4 *wrec = s_rec + wave * 64 * 3;
         const uint32_t *ent = a.b.entries + off + na;
         auto rec_of_entry = [&](uint32_t ri) { return (ri >= a.b.Acap && ri < a.b.Rcap) ? recv[ri] : kNoRec; };
+        // the colours of label changes enter the stored sums centred on the colour
+        // offset (c - 1/2): those sums then carry both signs, and their float rounding
+        // stays small against the differences that dL/dsigma takes of them
+        auto rec_of_entry_c = [&](uint32_t ri) {
+            Rec r = rec_of_entry(ri);
+            r.b.z -= kColorOffset;
+            r.b.w -= kColorOffset;
+            r.c.x -= kColorOffset;
+            return r;
+        };
         Rec cur = kNoRec;
         uint32_t ri_next = 0xffffffffu;
-        if (lane < nd) cur = rec_of_entry(ent[lane]);
+        if (lane < nd) cur = rec_of_entry_c(ent[lane]);
         if (64 + lane < nd) ri_next = ent[64 + lane];
         for (uint64_t base = 0; base < nd; base += 64) {
             const int cnt = (int)(nd - base < 64 ? nd - base : 64);
@@ -1042,7 +1063,7 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
             __builtin_amdgcn_wave_barrier();
             // next batch's records (their indices are here), the batch after's indices
             cur = kNoRec;
-            if (base + 64 + lane < nd) cur = rec_of_entry(ri_next);
+            if (base + 64 + lane < nd) cur = rec_of_entry_c(ri_next);
             ri_next = 0xffffffffu;
             if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
             const bool mine = (m & wbit) != 0;
@@ -1124,7 +1145,7 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
             const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
             const float dx = ra.x + colf;
             const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
-            blend_active<PPT>(ra, rb, rc, cb, cc, rowf, inmask, npair, P, Q, T);
+            blend_active<PPT>(ra, rb, rc, cb, cc, rowf, inmask, npair, P, Q, Qs, T);
           }
         }
     }
@@ -1171,12 +1192,13 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
         im[pix] = Tt * a.bg0 + (1.f - Tt) * F0;
         im[HW + pix] = Tt * a.bg1 + (1.f - Tt) * F1;
         im[2 * HW + pix] = Tt * a.bg2 + (1.f - Tt) * F2;
-        float *ps = a.pixstate + 5 * pb;
+        float *ps = a.pixstate + kPixStatePlanes * pb;
         ps[pix] = Tt;
         ps[HW + pix] = Qt;
         ps[2 * HW + pix] = F0;
         ps[3 * HW + pix] = F1;
         ps[4 * HW + pix] = F2;
+        ps[5 * HW + pix] = Qs[p];
     }
 }
 

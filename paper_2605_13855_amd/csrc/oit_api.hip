@@ -191,7 +191,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.scan_tmp = o; o = align256(o + 4 * nsums);
     p.ep = o; o = align256(o + 4 * kEpStride * pc);
     p.pixconst = o; o = align256(o + 16 * (size_t)p.total_px);
-    p.pixB = o; o = align256(o + 4 * (size_t)p.total_px);
+    p.pixB = o; o = align256(o + 8 * (size_t)p.total_px);
     p.sig_part = o; o = align256(o + 8 * (size_t)(kSigPixParts + kSigPreParts));
     p.tile_cnt = o; o = align256(o + 16 * (size_t)p.T);
     p.total = o;
@@ -228,7 +228,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.scan_tmp = (uint32_t *)(w + p.scan_tmp);
     b.ep = (float *)(w + p.ep);
     b.pixconst = (float4 *)(w + p.pixconst);
-    b.pixB = (float *)(w + p.pixB);
+    b.pixB = (float2 *)(w + p.pixB);
     b.sig_part = (double *)(w + p.sig_part);
     b.loss_part = (double *)(w + p.loss_part);
     b.tile_cnt = (unsigned long long *)(w + p.tile_cnt);

@@ -12,7 +12,9 @@ namespace oit {
 constexpr int kMaxViews = 64;
 constexpr int kBwdLanes = 64;   // splats per backward work item (one wave)
 constexpr int kScanThreads = 1024;
-constexpr int kEpStride = 12;                  // floats per entry partial (10 used, 16-byte rows)
+constexpr int kEpStride = 12;                  // floats per entry partial (11 used, 16-byte rows)
+constexpr int kEpUsed = 11;                    // screen-space partials per entry row
+constexpr int kPixStatePlanes = OIT_PIXSTATE_PLANES;   // T, Q, F (rgb), dQ/dsigma per pixel
 constexpr int kScanBlockItems = 256 * 16;      // values per block of the device-wide scan
 constexpr int kSortGrid = 1024;                // blocks of a radix-sort pass (each a contiguous range)
 constexpr int kRadixBits = 5;                  // digit width of a radix-sort pass
@@ -76,7 +78,7 @@ struct Buffers {
     uint32_t *scan_tmp;                         // block sums of the device-wide scans
     float *ep;                                  // [pair_cap][kEpStride] screen-space partials, by unsorted slot
     float4 *pixconst;                           // [total_px] (A_r, A_g, A_b, -s1)
-    float *pixB;                                // [total_px] B
+    float2 *pixB;                               // [total_px] (B, lambda = (dQ/dsigma) / Q)
     double *sig_part;                           // [kSigPixParts + kSigPreParts] per-block shares of dL/dsigma
     double *loss_part;                          // [kSigPixParts] per-block shares of the L1 loss
     unsigned long long *tile_cnt;               // [T][2] contributing / evaluated active pairs per tile

@@ -23,6 +23,7 @@ STATUS_DELTA_OVERFLOW = 4
 SELECT_TOPK = 0
 SELECT_THRESHOLD = 1
 MAX_VIEWS = 64
+PIXSTATE_PLANES = 6   # T, Q, F (rgb), dQ/dsigma (OIT_PIXSTATE_PLANES)
 GROUPS = (("mean", 3), ("log_scale", 3), ("quat", 4), ("opacity_logit", 1), ("sh", 48), ("vsh", 16))
 
 

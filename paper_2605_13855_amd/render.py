@@ -74,7 +74,7 @@ class Renderer:
         self._alloc_ws()
         dev = self.device
         self._image_buf = torch.zeros(3 * self.total_px, device=dev)
-        self._pixstate_buf = torch.zeros(5 * self.total_px, device=dev)
+        self._pixstate_buf = torch.zeros(oit.PIXSTATE_PLANES * self.total_px, device=dev)
         self.image = self._image_buf
         self.pixstate = self._pixstate_buf
 
@@ -98,11 +98,11 @@ class Renderer:
             raise oit.OITError(oit.lib.oit_last_error().decode())
         if nb > self.ws.numel():
             self._alloc_ws()
-        if 5 * self.total_px > self._pixstate_buf.numel():
+        if oit.PIXSTATE_PLANES * self.total_px > self._pixstate_buf.numel():
             self._image_buf = torch.zeros(3 * self.total_px, device=self.device)
-            self._pixstate_buf = torch.zeros(5 * self.total_px, device=self.device)
+            self._pixstate_buf = torch.zeros(oit.PIXSTATE_PLANES * self.total_px, device=self.device)
         self.image = self._image_buf[:3 * self.total_px]
-        self.pixstate = self._pixstate_buf[:5 * self.total_px]
+        self.pixstate = self._pixstate_buf[:oit.PIXSTATE_PLANES * self.total_px]
 
     def set_tuning(self, tile=None, batch=None, pair_capacity=None, bwd_mode=None):
         self.tuning = oit.Tuning(int(tile or self.tuning.tile), int(batch or self.tuning.batch),

@@ -10,7 +10,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2605_13855_amd import scenes
-from tests.gpu_common import GRAD_RTOL, IMAGE_RTOL, grad_floor, grad_rel, sigma_ok, to_np
+from tests.gpu_common import IMAGE_RTOL, compare_grads, sigma_ok, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -49,14 +49,18 @@ def near_pixels(sc, cam, xs, ys):
     return bad
 
 
-def run_case(sc, n_px, seed, active_fraction=None, tile=16):
+def run_case(sc, n_px, seed, active_fraction=None, tile=16, batch=64, reselect=False):
+    """reselect: after a first forward (every label change +1: the complement of A enters
+    pre), select again from new scores and render with that second step's label changes,
+    which have both signs, as every step of the benchmark's training loop does."""
     rng = np.random.default_rng(seed)
+    torch.manual_seed(seed)
     params = params_to_device(sc.params)
     sigma = torch.tensor([sc.sigma], device=DEV)
     n = sc.n
     act = pre = None
     if active_fraction is None:
-        r = Renderer(sc.cameras, n, tile=tile)
+        r = Renderer(sc.cameras, n, tile=tile, batch=batch)
         r.fit_pair_capacity(params, sigma, sc.background)
     else:
         k = int(np.ceil(active_fraction * n))
@@ -74,8 +78,16 @@ def run_case(sc, n_px, seed, active_fraction=None, tile=16):
         act = {"idx": idx, "n": na, "delta_idx": didx, "delta_sign": dsg, "n_delta": nd}
         total_px = sum(c.width * c.height for c in sc.cameras)
         pre = torch.zeros(9 * total_px, device=DEV)
-        r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=n, tile=tile)
+        r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=n, tile=tile, batch=batch)
         r.fit_pair_capacity(params, sigma, sc.background, act, pre)
+        if reselect:
+            r.forward(params, sigma, sc.background, act, pre)
+            oit.update_active_set(torch.rand(n, device=DEV), n, 0, k, 0.0, label, idx, na, didx, dsg, nd, sws)
+            signs = dsg[:int(nd.item())].cpu().numpy()
+            log(f"  second selection: {int(nd.item())} label changes, {int((signs < 0).sum())} into A, "
+                f"{int((signs > 0).sum())} out of A")
+            assert (signs < 0).any() and (signs > 0).any()
+            r.fit_pair_capacity(params, sigma, sc.background, act, pre)
     r.forward(params, sigma, sc.background, act, pre)
     torch.cuda.synchronize()
     assert r.status() == 0
@@ -116,11 +128,7 @@ def run_case(sc, n_px, seed, active_fraction=None, tile=16):
         tot = gr if tot is None else {k: tot[k] + gr[k] for k in tot}
     sel = np.arange(n) if act is None else act["idx"][:rows].cpu().numpy()
     ref = {k: v[:, sel] for k, v in tot.items()}
-    fl = grad_floor(ref)
-    for name, _ in O.GROUPS:
-        rel, den = grad_rel(to_np(g_gpu[name])[:, :rows], ref[name], fl)
-        log(f"  grad {name}: rel {rel:.2e} (norm {den:.3e})")
-        assert rel <= GRAD_RTOL
+    compare_grads({g: to_np(g_gpu[g])[:, :rows] for g, _ in O.GROUPS}, ref, log)
     ok, srel = sigma_ok(float(gsig.item()), s_ref, s_abs)
     log(f"  grad sigma: gpu {float(gsig.item()):.6e} oracle {s_ref:.6e} (sum |terms| {s_abs:.3e}) rel {srel:.2e}")
     assert ok
@@ -136,8 +144,18 @@ def test_config3_dense_and_active_sampled():
 
 def test_config4_batched_active_sampled():
     sc = scenes.make_scene(4)
-    log("config 4, 5% active, 16 uneven views in one launch (tile 32, batch 64: the benchmark's launch)")
+    log("config 4, 5% active, 16 uneven views in one launch (tile 32, batch 64)")
     run_case(sc, 24, 5, active_fraction=0.05, tile=32)
+
+
+@pytest.mark.parametrize("batch", [64, 128])
+def test_config4_timed_step_second_selection(batch):
+    """The benchmark's steady-state forward: config 4 at tile 32 with the label changes
+    of a second top-k selection (both signs) folded into pre in the same launch as the
+    active entries (App. A, BAN + BAU), at the LDS batches the tuner picks."""
+    sc = scenes.make_scene(4)
+    log(f"config 4, 5% active, second selection, tile 32, batch {batch}")
+    run_case(sc, 24, 7 + batch, active_fraction=0.05, tile=32, batch=batch, reselect=True)
 
 
 def test_config5_clusters_sampled():

@@ -10,8 +10,8 @@ import torch
 
 from oracle import oracle as O
 from paper_2605_13855_amd import scenes
-from tests.gpu_common import (GRAD_RTOL, IMAGE_RTOL, NEAR_MARGIN, compare_image, grad_floor, grad_rel,
-                              image_views, oracle_grads, sigma_ok, to_np)
+from tests.gpu_common import (IMAGE_RTOL, NEAR_MARGIN, compare_grads, compare_image, image_views, oracle_grads,
+                              sigma_ok, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,15 @@ DEV = "cuda"
 
 def log(msg):
     print(msg, flush=True)
+
+
+def mask_near(g_views, nears):
+    """Zero dL/dC at the pixels that a float-ambiguous pair (alpha within NEAR_MARGIN of
+    1/255) touches: there float32 and FP64 may take different contribution decisions,
+    and the flipped pair's own term (about alpha dL/dalpha / 255) would show in the
+    per-row gradient check of its splat.  Both sides get the masked dL/dC."""
+    for g, near in zip(g_views, nears):
+        g[:, near] = 0.0
 
 
 def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True, windows=None, seed=0,
@@ -39,11 +48,13 @@ def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True,
     torch.cuda.synchronize()
     assert r.status() == 0
     imgs = image_views(r, r.image, 3)
-    states = image_views(r, r.pixstate, 5)
+    states = image_views(r, r.pixstate, oit.PIXSTATE_PLANES)
     worst = 0.0
     masked = 0
+    nears = []
     for k, cam in enumerate(sc.cameras):
         ref = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=near_margin)
+        nears.append(ref["near"])
         err = compare_image(imgs[k], ref["image"], ref["near"])
         masked += int(ref["near"].sum())
         worst = max(worst, err)
@@ -57,6 +68,7 @@ def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True,
         return r
     rng = np.random.default_rng(seed)
     g_views = [rng.normal(size=(3, c.height, c.width)) for c in sc.cameras]
+    mask_near(g_views, nears)
     if windows:
         for k, w in enumerate(windows):
             m = np.zeros_like(g_views[k])
@@ -72,11 +84,7 @@ def dense_case(sc, tile=16, batch=64, near_margin=NEAR_MARGIN, check_grads=True,
     g_ref, s_ref, s_abs = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras,
                                        [g.astype(np.float32).astype(np.float64) for g in g_views], windows,
                                        with_abs=True)
-    fl = grad_floor(g_ref)
-    for name, _ in O.GROUPS:
-        rel, den = grad_rel(to_np(g_gpu[name]), g_ref[name], fl)
-        log(f"  grad {name}: rel {rel:.2e} (norm {den:.3e})")
-        assert rel <= GRAD_RTOL, (name, rel)
+    compare_grads({g: to_np(g_gpu[g]) for g, _ in O.GROUPS}, g_ref, log)
     ok, srel = sigma_ok(float(gsig.item()), s_ref, s_abs)
     log(f"  grad sigma: gpu {float(gsig.item()):.6e} oracle {s_ref:.6e} (sum |terms| {s_abs:.3e}) rel {srel:.2e}")
     assert ok or abs(float(gsig.item()) - s_ref) <= sigma_atol
@@ -244,6 +252,9 @@ def test_l1_loss_on_the_render_workspace_keeps_the_backward_exact():
         gi = torch.zeros_like(r.image)
         loss = torch.zeros(1, dtype=torch.float64, device=DEV)
         oit.l1_loss(r.image, tgt, r.cams_arr, r.n_views, gi, loss, r.ws)
+        for v, cam in zip(r.views(gi, 3), sc.cameras):
+            near = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)["near"]
+            v[:, torch.tensor(near, device=DEV)] = 0.0
         g_gpu = new_grads(r.cap.active_capacity, DEV)
         gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
         r.backward(params, sigma, sc.background, gi, g_gpu, gsig, act, pre)
@@ -252,11 +263,18 @@ def test_l1_loss_on_the_render_workspace_keeps_the_backward_exact():
         g_views = [to_np(v) for v in r.views(gi, 3)]
         g_ref, _ = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras, g_views)
         ref = {kk: v[:, rows] for kk, v in g_ref.items()}
-        fl = grad_floor(ref)
-        for name, _ in O.GROUPS:
-            rel, _ = grad_rel(to_np(g_gpu[name])[:, :len(rows)], ref[name], fl)
-            log(f"  tile {tile} active {frac}: grad {name} rel {rel:.2e}")
-            assert rel <= GRAD_RTOL, (tile, name, rel)
+        compare_grads({g: to_np(g_gpu[g])[:, :len(rows)] for g, _ in O.GROUPS}, ref, log,
+                      f"tile {tile} active {frac}: ")
+
+
+def pre_sums(planes):
+    """The stored pre-rendered accumulators [9][H][W] as the plain sums the oracle
+    gives: the buffer keeps its colour sums centred on the colour offset 1/2, so
+    P0 = P0' + Q0 / 2 and P1 = P1' + Q1 / 2."""
+    out = np.array(planes, dtype=np.float64, copy=True)
+    out[0:3] += 0.5 * out[6]
+    out[3:6] += 0.5 * out[7]
+    return out
 
 
 def r_total_px(sc):
@@ -409,10 +427,15 @@ def test_sparse_adam_leaves_inactive_rows_bitwise():
         assert not torch.equal(params[g][idx.long()], before[g][idx.long()])
 
 
-def test_active_set_render_equals_dense():
+@pytest.mark.parametrize("tile,batch", [(16, 64), (32, 32), (32, 64), (32, 128), (32, 256)])
+def test_active_set_render_equals_dense(tile, batch):
     """Active splats rendered against the pre-rendered inactive set give the dense image
-    and, on the active rows, the dense gradients (Sec. 4.1)."""
-    log("active set vs dense, 2 views")
+    and, on the active rows, the dense gradients (Sec. 4.1) -- after a first selection
+    (every label change leaves A: sign +1) and after a second one, whose label changes
+    have both signs (splats leaving pre and joining it in the same pass: App. A, BAU).
+    Tile 32 runs the forward variant with label changes at six waves per SIMD, the
+    launch of the timed step, at every LDS batch."""
+    log(f"active set vs dense, 2 views, tile {tile}, batch {batch}")
     sc = scenes.random_scene(31, 4000, 96, 80, n_views=2, mean_range=1.0)
     n = sc.n
     params = params_to_device(sc.params)
@@ -430,7 +453,7 @@ def test_active_set_render_equals_dense():
            "delta_sign": torch.tensor(dsg, dtype=torch.int8, device=DEV),
            "n_delta": torch.tensor([len(didx)], dtype=torch.int32, device=DEV)}
     pre = torch.zeros(9 * total_px, device=DEV)
-    r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=len(didx), tile=16)
+    r = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=len(didx), tile=tile, batch=batch)
     r.fit_pair_capacity(params, sigma, sc.background, act, pre)
     r.forward(params, sigma, sc.background, act, pre)
     torch.cuda.synchronize()
@@ -439,18 +462,22 @@ def test_active_set_render_equals_dense():
     pres = image_views(r, pre, 9)
     inactive = np.ones(n, bool)
     inactive[idx] = False
+    nears = []
     for v, cam in enumerate(sc.cameras):
         dense = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)
+        nears.append(dense["near"])
         err = compare_image(imgs[v], dense["image"], dense["near"])
         log(f"  view {v}: active-set image vs dense oracle err {err:.2e}")
         assert err <= IMAGE_RTOL
         ref_pre = O.render(sc.params, sc.sigma, sc.background, cam, include=inactive.astype(np.uint8))["pre"]
         ok = ~dense["near"]
+        got = pre_sums(pres[v])
         for p in range(9):
-            rel = np.abs(pres[v][p][ok] - ref_pre[p][ok]).max() / max(np.abs(ref_pre[p]).max(), 1e-30)
+            rel = np.abs(got[p][ok] - ref_pre[p][ok]).max() / max(np.abs(ref_pre[p]).max(), 1e-30)
             assert rel < 1e-4, (v, p, rel)
     # gradients on the active rows equal the dense gradients restricted to A
     g_views = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cameras]
+    mask_near(g_views, nears)
     gimg = r.pack(g_views)
     g_gpu = new_grads(k, DEV)
     gsig = torch.zeros(1, dtype=torch.float64, device=DEV)
@@ -458,11 +485,8 @@ def test_active_set_render_equals_dense():
     torch.cuda.synchronize()
     g_ref, s_ref, s_abs = oracle_grads(sc.params, sc.sigma, sc.background, sc.cameras,
                                        [g.astype(np.float64) for g in g_views], with_abs=True)
-    fl = grad_floor({k: v[:, idx] for k, v in g_ref.items()})
-    for name, _ in O.GROUPS:
-        rel, _ = grad_rel(to_np(g_gpu[name])[:, :len(idx)], g_ref[name][:, idx], fl)
-        log(f"  active grad {name}: rel {rel:.2e}")
-        assert rel <= GRAD_RTOL
+    compare_grads({g: to_np(g_gpu[g])[:, :len(idx)] for g, _ in O.GROUPS},
+                  {g: v[:, idx] for g, v in g_ref.items()}, log, "active: ")
     ok, srel = sigma_ok(float(gsig.item()), s_ref, s_abs)
     log(f"  sigma (active + pre part) rel {srel:.2e}")
     assert ok
@@ -475,19 +499,34 @@ def test_active_set_render_equals_dense():
             "delta_idx": torch.tensor(didx2, dtype=torch.int32, device=DEV),
             "delta_sign": torch.tensor(dsg2, dtype=torch.int8, device=DEV),
             "n_delta": torch.tensor([len(didx2)], dtype=torch.int32, device=DEV)}
+    assert (dsg2 > 0).any() and (dsg2 < 0).any(), "the second selection changes labels both ways"
     pre_before = pre.clone()
-    r2 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=16)
+    r2 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=tile, batch=batch)
     r2.fit_pair_capacity(params, sigma, sc.background, act2, pre)
     r2.forward(params, sigma, sc.background, act2, pre)
+    torch.cuda.synchronize()
+    assert r2.status() == 0
     imgs2 = image_views(r2, r2.image, 3)
     for v, cam in enumerate(sc.cameras):
         dense = O.render(sc.params, sc.sigma, sc.background, cam, near_margin=NEAR_MARGIN)
         err = compare_image(imgs2[v], dense["image"], dense["near"])
         log(f"  after label changes, view {v}: err {err:.2e}")
         assert err <= IMAGE_RTOL
+    # gradients of the second step's active rows, sigma with its pre part
+    g_gpu2 = new_grads(k, DEV)
+    gsig2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    r2.backward(params, sigma, sc.background, gimg, g_gpu2, gsig2, act2, pre)
+    torch.cuda.synchronize()
+    assert r2.status() == 0
+    compare_grads({g: to_np(g_gpu2[g])[:, :len(idx2)] for g, _ in O.GROUPS},
+                  {g: v[:, idx2] for g, v in g_ref.items()}, log, "second selection: ")
+    ok, srel = sigma_ok(float(gsig2.item()), s_ref, s_abs)
+    log(f"  second selection: sigma rel {srel:.2e}")
+    assert ok
     # the same pass from a pair capacity far too small through forward_fitted: the lists
     # overflow, the capacity grows, the pre buffer gets its label changes exactly once
-    r3 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=16, pair_capacity=100)
+    r3 = Renderer(sc.cameras, n, active_capacity=k, delta_capacity=max(len(didx2), 1), tile=tile, batch=batch,
+                  pair_capacity=100)
     r3.forward_fitted(params, sigma, sc.background, act2, pre_before)
     torch.cuda.synchronize()
     assert r3.tuning.pair_capacity > 100 and r3.status() == 0
