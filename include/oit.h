@@ -272,6 +272,26 @@ oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, in
                                  void *ws, size_t ws_bytes, oit_stream stream);
 
 /*
+ * oit_update_active_set without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The library calls no allocator: its scratch is a static device
+ * array of oit_select_workspace_bytes(OIT_NOALLOC_SELECT_MAX_N) bytes (about 4.3 MB),
+ * one per GPU the library runs on, held until the process ends.
+ * n           1 .. OIT_NOALLOC_SELECT_MAX_N splats; larger n is OIT_ERR_INVALID.
+ * status      [1] device int32 out: cleared, then given the overflow bits that
+ *             oit_update_active_set sets in its workspace's status word.
+ * Other arguments and results as oit_update_active_set.  All calls on one GPU share
+ * that GPU's scratch, which keeps the last call's contents: calls that overlap on one
+ * GPU (concurrent streams, or host threads) race and must be serialised by the caller.
+ */
+#define OIT_NOALLOC_SELECT_MAX_N (1LL << 22)
+oit_status oit_update_active_set_noalloc(const float *score, int64_t n, int32_t mode, int64_t k, float thresh,
+                                         uint8_t *label, int32_t *active_idx, int64_t active_capacity,
+                                         int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign,
+                                         int64_t delta_capacity, int32_t *n_delta, int32_t *status,
+                                         oit_stream stream);
+
+/*
  * Label changes between two label arrays (for pre-rendered buffers that fell behind
  * several active-set updates: the paper delays the pre-render update of a view until
  * the view is next used, Sec. 4.1 "Implementation Details").

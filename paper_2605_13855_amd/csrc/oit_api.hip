@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "oit_density.h"
@@ -334,6 +335,48 @@ oit_status l1_plan(const oit_camera *cams, int32_t n_views, Plan &p)
 
 }  // namespace
 
+namespace {
+constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// bytes of the selection workspace for n splats (the layout of select_buffers)
+constexpr size_t select_bytes(int64_t n)
+{
+    return align256c(align256c(align256c(align256c(align256c(4) + 4 * 8) + 4 * 2048) +
+                               4 * 3 * (size_t)((n + 1023) / 1024 + 1)) +
+                     (size_t)n);
+}
+
+// The no-allocation selection's scratch: one file-scope array per device, held until
+// the process ends.  Host code never uses its name as an address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress, once per device.
+constexpr int64_t kNoAllocMaxN = OIT_NOALLOC_SELECT_MAX_N;
+constexpr size_t kNoAllocBytes = select_bytes(kNoAllocMaxN);
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch array (resolved on the first call)
+oit_status scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(OIT_ERR_HIP, "no-allocation selection: current device %d unusable", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(OIT_ERR_HIP, "no-allocation selection: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return OIT_OK;
+}
+}  // namespace
+
 extern "C" {
 
 size_t oit_l1_loss_workspace_bytes(void)
@@ -507,14 +550,7 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
 size_t oit_select_workspace_bytes(int64_t n)
 {
     if (n <= 0) return 0;
-    const int64_t nblk = (n + 1023) / 1024;
-    size_t o = 0;
-    o = align256(o + 4);              // status
-    o = align256(o + 4 * 8);          // state
-    o = align256(o + 4 * 2048);       // hist
-    o = align256(o + 4 * 3 * (size_t)(nblk + 1));
-    o = align256(o + (size_t)n);      // flags
-    return o;
+    return select_bytes(n);
 }
 
 oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, int64_t k, float thresh,
@@ -540,6 +576,37 @@ oit_status oit_update_active_set(const float *score, int64_t n, int32_t mode, in
     return check_launch("oit_update_active_set");
 }
 
+
+oit_status oit_update_active_set_noalloc(const float *score, int64_t n, int32_t mode, int64_t k, float thresh,
+                                         uint8_t *label, int32_t *active_idx, int64_t active_capacity,
+                                         int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign,
+                                         int64_t delta_capacity, int32_t *n_delta, int32_t *status,
+                                         oit_stream stream)
+{
+    if (n <= 0 || n > kNoAllocMaxN)
+        return fail(OIT_ERR_INVALID, "oit_update_active_set_noalloc: n = %lld outside [1, %lld] (its static scratch)",
+                    (long long)n, (long long)kNoAllocMaxN);
+    if (mode != OIT_SELECT_TOPK && mode != OIT_SELECT_THRESHOLD)
+        return fail(OIT_ERR_INVALID, "mode = %d unknown", mode);
+    if (!score || !label || !active_idx || !n_active || !delta_idx || !delta_sign || !n_delta || !status)
+        return fail(OIT_ERR_INVALID, "oit_update_active_set_noalloc: NULL buffer");
+    if (active_capacity <= 0 || delta_capacity <= 0)
+        return fail(OIT_ERR_INVALID, "capacities must be positive");
+    if (mode == OIT_SELECT_THRESHOLD && !std::isfinite(thresh))
+        return fail(OIT_ERR_INVALID, "threshold must be finite");
+    void *base = nullptr;
+    const oit_status st = scratch_address(&base);
+    if (st != OIT_OK) return st;
+    // the scratch keeps the last call's contents: the selection kernels clear or fully
+    // write everything they read, and the status word is the caller's, cleared here
+    SelectBuffers sb = select_buffers(base, n);
+    sb.status = status;
+    const hipStream_t s = (hipStream_t)stream;
+    fill_u32((uint32_t *)status, 1, 0u, s);
+    launch_select(score, n, mode, k, thresh, label, active_idx, active_capacity, n_active, delta_idx, delta_sign,
+                  delta_capacity, n_delta, sb, s);
+    return check_launch("oit_update_active_set_noalloc");
+}
 
 oit_status oit_label_delta(const uint8_t *old_label, const uint8_t *new_label, int64_t n, int32_t *active_idx,
                            int64_t active_capacity, int32_t *n_active, int32_t *delta_idx, int8_t *delta_sign,

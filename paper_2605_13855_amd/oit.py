@@ -76,6 +76,7 @@ def _load():
     L.oit_select_workspace_bytes.argtypes = [I64]
     L.oit_select_workspace_bytes.restype = SZ
     L.oit_update_active_set.argtypes = [P, I64, I32, I64, F, P, P, I64, P, P, P, I64, P, P, SZ, P]
+    L.oit_update_active_set_noalloc.argtypes = [P, I64, I32, I64, F, P, P, I64, P, P, P, I64, P, P, P]
     L.oit_sparse_adam_step.argtypes = [P, P, P, P, P, P, I64, P, F, F, F, P, P]
     L.oit_sigma_adam_step.argtypes = [P, P, P, P, F, F, F, F, P, P]
     L.oit_read_status.argtypes = [P, SZ, P, P]
@@ -98,6 +99,7 @@ def _load():
     L.oit_last_error.argtypes = []
     L.oit_last_error.restype = ctypes.c_char_p
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
+              L.oit_update_active_set_noalloc,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
               L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_label_delta,
               L.oit_fps_views, L.oit_densify_stats, L.oit_densify_plan, L.oit_densify_apply,
@@ -220,6 +222,20 @@ def update_active_set(score, n, mode, k, thresh, label, active_idx, n_active, de
                                    _ptr(delta_sign), delta_idx.numel(), _ptr(n_delta), _ptr(ws), ws.numel(),
                                    _stream(stream))
     _check(rc, "oit_update_active_set")
+
+
+NOALLOC_SELECT_MAX_N = 1 << 22   # OIT_NOALLOC_SELECT_MAX_N
+
+
+def update_active_set_noalloc(score, n, mode, k, thresh, label, active_idx, n_active, delta_idx, delta_sign,
+                              n_delta, status, stream=None):
+    """update_active_set without a workspace (the library's static per-GPU scratch);
+    status: [1] device int32 output of the overflow bits."""
+    rc = lib.oit_update_active_set_noalloc(_ptr(score), int(n), int(mode), int(k), float(thresh), _ptr(label),
+                                           _ptr(active_idx), active_idx.numel(), _ptr(n_active), _ptr(delta_idx),
+                                           _ptr(delta_sign), delta_idx.numel(), _ptr(n_delta), _ptr(status),
+                                           _stream(stream))
+    _check(rc, "oit_update_active_set_noalloc")
 
 
 def label_delta(old_label, new_label, n, active_idx, n_active, delta_idx, delta_sign, n_delta, ws, stream=None):

@@ -55,6 +55,13 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert rc == -1
     assert oit.lib.oit_select_workspace_bytes(0) == 0
     assert oit.lib.oit_select_workspace_bytes(5000) > 5000
+    # the no-allocation selection refuses sizes beyond its static scratch on the host
+    rc = oit.lib.oit_update_active_set_noalloc(None, oit.NOALLOC_SELECT_MAX_N + 1, 0, 5, 0.0, None, None, 0, None,
+                                               None, None, 0, None, None, None)
+    assert rc == -1 and b"scratch" in oit.lib.oit_last_error()
+    rc = oit.lib.oit_update_active_set_noalloc(None, 10, 0, 5, 0.0, None, None, 0, None, None, None, 0, None, None,
+                                               None)
+    assert rc == -1
 
 
 def test_workspace_grows_with_views_and_capacity(lib):
