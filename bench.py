@@ -78,6 +78,77 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Algorithmic HBM bytes per unit of each stage (float32 data; N splats, V views, R listed
+# records = active rows + label changes, E tile entries of the call, px pixels):
+#   select          6 B per splat (score read, label read and written) + 4 B per active
+#                   index + 5 B per label change
+#   preprocess      300 B of parameters per listed record + 60 B per (record, view):
+#                   the 48-byte record, its tile rectangle and hit count
+#   binning         40 B per tile entry: the list's key, slot and record written and the
+#                   stable sort's passes over them
+#   raster fwd      52 B per entry (index and record staged per tile) + 36 B per pixel
+#                   (image and pixel state written); bound by the FP32 VALU, whose work
+#                   is 10 flops per evaluated (splat, pixel) pair + 14 per contributing
+#                   one (the label changes' blends are not counted)
+#   loss            36 B per pixel (image and target read, dL/dC written)
+#   pixel consts    60 B per pixel (state and dL/dC read, constants written), +32 B with
+#                   a pre-rendered buffer
+#   raster bwd      104 B per entry (index, slot, record, partials row) + 24 B per pixel
+#                   (constants); VALU: 10 flops per evaluated pair + 41 per contributing
+#   preprocess bwd  44 B per entry (partials row) + 604 B per active row (parameters
+#                   read, gradients and score written)
+#   adam            2100 B per active row (parameters, gradient, both moments)
+def stage_work(run, n, views, px, dense):
+    """{stage: (bound, algorithmic bytes or flops)} of one step of `run`."""
+    k = run["active"]
+    d = run["kernel_deltas"]
+    rec = k + d
+    e = run["kernel_entries"]
+    ev, pc = run["kernel_evals"], run["kernel_pairs"]
+    w = {"preprocess": ("hbm", 300.0 * rec + 60.0 * rec * views),
+         "binning": ("hbm", 40.0 * e),
+         "raster_fwd": ("alu", ev * FWD_FLOP_EVAL + pc * FWD_FLOP_CONTRIB),
+         "loss": ("hbm", 36.0 * px),
+         "pixconst": ("hbm", (60.0 if dense else 92.0) * px),
+         "raster_bwd": ("alu", ev * BWD_FLOP_EVAL + pc * BWD_FLOP_CONTRIB),
+         "preprocess_bwd": ("hbm", 44.0 * e + 604.0 * k),
+         "adam": ("hbm", 2100.0 * k)}
+    if not dense:
+        w["select"] = ("hbm", 6.0 * n + 4.0 * k + 5.0 * d)
+    return w
+
+
+def stage_roofs(run, n, views, px, dense):
+    """Each stage's time (eager timing pass, median) and its fraction of its binding roof."""
+    out = {}
+    for name, (bound, work) in stage_work(run, n, views, px, dense).items():
+        ms = run["stages_ms"].get(name)
+        if ms is None or ms <= 0:
+            continue
+        rate = work / (ms * 1e-3)
+        if bound == "hbm":
+            out[name] = {"ms": round(ms, 4), "bound": "hbm", "alg_bytes": work,
+                         "GB_s": round(rate / 1e9, 1), "frac": round(rate / 1e9 / PEAK_HBM_GBS, 4)}
+        else:
+            out[name] = {"ms": round(ms, 4), "bound": "alu", "alg_flops": work,
+                         "TFLOP_s": round(rate / 1e12, 2), "frac": round(rate / 1e12 / PEAK_FP32_TFLOPS, 4)}
+    return out
+
+
+def step_bytes(run, n, views, px, dense):
+    """Algorithmic HBM bytes of one whole step (every stage's, the raster stages' bytes
+    included) and its FP32 flops."""
+    e = run["kernel_entries"]
+    tot, flops = 0.0, 0.0
+    for name, (bound, work) in stage_work(run, n, views, px, dense).items():
+        if bound == "hbm":
+            tot += work
+        else:
+            flops += work
+    tot += 52.0 * e + 36.0 * px + 104.0 * e + 24.0 * px
+    return tot, flops
+
+
 def prime(trainer):
     """First iterations, eager, with the pair capacity fitted before each; returns the
     largest number of tile entries they needed.  In the active form the first selection
@@ -101,7 +172,37 @@ def prime(trainer):
     return need
 
 
-def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=False):
+def timed_iteration(t):
+    """One eager iteration with events at the boundaries of the ABI calls (select, render
+    forward, loss, render backward, Adam); with the library's timing on, the render calls
+    also record their inner stages.  Returns {stage: ms}."""
+    import torch
+    from paper_2605_13855_amd import oit
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    ev[0].record()
+    if not t.dense:
+        t.select()
+    ev[1].record()
+    pre = None if t.dense else t.pre
+    t.r.forward(t.params, t.sigma, t.bg, t._active(), pre)
+    ev[2].record()
+    t.loss_fn(t.r, t.r.image, t.target, t.grad_image, t.loss)
+    ev[3].record()
+    t.backward()
+    ev[4].record()
+    t.optimise()
+    ev[5].record()
+    torch.cuda.synchronize()
+    out = oit.timing_read_stages()
+    out["select"] = ev[0].elapsed_time(ev[1])
+    out["loss"] = ev[2].elapsed_time(ev[3])
+    out["adam"] = ev[4].elapsed_time(ev[5])
+    out["forward_call"] = ev[1].elapsed_time(ev[2])
+    out["backward_call"] = ev[3].elapsed_time(ev[4])
+    return out
+
+
+def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=False, late_gap=0):
     """Time one form of the step.  The autotuner, if asked, runs on a throwaway trainer,
     so the timed trainer starts from the same state with or without it.  Graph replays
     (or eager steps) give the step time; a short eager pass after them times the
@@ -141,35 +242,58 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     torch.cuda.synchronize()
     oit.clear_status(t.r.ws)
     log(f"{name}: timing {steps} {'eager steps' if eager else 'graph replays'}")
-    step_ms, pairs, evals, entries, chunks, boxes = [], [], [], [], [], []
-    for _ in range(steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        step()
-        e1.record()
-        torch.cuda.synchronize()
-        step_ms.append(e0.elapsed_time(e1))
-        c = t.r.counters()
-        entries.append(c[0])
-        pairs.append(c[1])
-        evals.append(c[2])
-        chunks.append(c[3])
-        boxes.append(c[4])
+    def timed_window():
+        """`steps` timed steps; per step its time, label changes and the counters."""
+        w = {k: [] for k in ("ms", "deltas", "entries", "pairs", "evals", "chunks", "boxes")}
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step()
+            e1.record()
+            torch.cuda.synchronize()
+            w["ms"].append(e0.elapsed_time(e1))
+            if not t.dense:
+                w["deltas"].append(int(t.n_delta.item()))
+            c = t.r.counters()
+            for key, x in zip(("entries", "pairs", "evals", "chunks", "boxes"), c):
+                w[key].append(x)
+        return w
+
+    win = timed_window()
+    step_ms, pairs, evals, entries, chunks, boxes = (win[k] for k in ("ms", "pairs", "evals", "entries", "chunks",
+                                                                      "boxes"))
+    deltas = win["deltas"]
     # kernel timing pass: eager steps with kernel-bracketing events, and the pair
     # counters of the same launches
     ksteps = max(3, steps // 2)
     oit.timing_enable(True)
-    fwd_ms, bwd_ms, kpairs, kevals = [], [], [], []
+    fwd_ms, bwd_ms, kpairs, kevals, kentries, kdeltas, stage_ms = [], [], [], [], [], [], []
     for _ in range(ksteps):
-        t.iteration()
+        stage_ms.append(timed_iteration(t))
         f, b = oit.timing_read()
         fwd_ms.append(f)
         bwd_ms.append(b)
+        kdeltas.append(0 if t.dense else int(t.n_delta.item()))
         c = t.r.counters()
+        kentries.append(c[0])
         kpairs.append(c[1])
         kevals.append(c[2])
     oit.timing_enable(False)
     torch.cuda.synchronize()
+    stages = {k: statistics.median(d[k] for d in stage_ms) for k in stage_ms[0]}
+    late = None
+    if late_gap > 0:
+        # a later window of the same run: the active set keeps moving as training goes on
+        for _ in range(late_gap):
+            step()
+        torch.cuda.synchronize()
+        lw = timed_window()
+        late = {"after_steps": warmup + steps + ksteps + late_gap, "ms_per_step": round(statistics.mean(lw["ms"]), 4),
+                "ms_median": round(statistics.median(lw["ms"]), 4),
+                "contributing_pairs": statistics.mean(lw["pairs"]), "tile_entries": statistics.mean(lw["entries"])}
+        if lw["deltas"]:
+            late["label_changes_per_step"] = round(statistics.mean(lw["deltas"]), 1)
+        log(f"{name}: late window after {late['after_steps']} steps: {late['ms_per_step']:.3f} ms/step")
     st = t.r.status()
     if st:
         raise RuntimeError(f"device status {st} during the timed steps")
@@ -182,6 +306,11 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         "kernel_steps": ksteps,
         "kernel_pairs": statistics.mean(kpairs),
         "kernel_evals": statistics.mean(kevals),
+        "kernel_entries": statistics.mean(kentries),
+        "kernel_deltas": statistics.mean(kdeltas),
+        "stages_ms": stages,
+        "label_changes": deltas,
+        "late": late,
         "pairs": statistics.mean(pairs),
         "evals": statistics.mean(evals),
         "entries": statistics.mean(entries),
@@ -324,34 +453,67 @@ def densify_bench(scene, iters, interval, keep_probability, tile, batch, fractio
     return out
 
 
-def cpu_baseline(scene, budget_s=20.0):
-    """The FP64 oracle, single-threaded, on a window of view 0 (all splats), fwd + bwd."""
+_CPU_SCENE = None   # the scene the oracle workers read (set before they are forked)
+
+
+def _oracle_window(win):
+    """The FP64 oracle's forward and backward on one window of view 0, all splats
+    (dL/dC random inside the window); returns (contributing pairs, seconds)."""
     import numpy as np
     from oracle import oracle as O
+    sc = _CPU_SCENE
+    cam = sc.cameras[0]
+    x0, y0, x1, y1 = win
+    t0 = time.perf_counter()
+    r = O.render(sc.params, sc.sigma, sc.background, cam, window=win)
+    g = np.zeros((3, cam.height, cam.width))
+    g[:, y0:y1, x0:x1] = np.random.default_rng(x0 * 7919 + y0).normal(size=(3, y1 - y0, x1 - x0))
+    O.backward(sc.params, sc.sigma, sc.background, cam, g, window=win)
+    return r["pairs"], time.perf_counter() - t0
+
+
+def cpu_baseline(scene, budget_s=20.0):
+    """The FP64 oracle as it stands (single-threaded C), fwd + bwd on windows of view 0
+    with all splats: first one process on a centre window sized to about half the
+    budget, then one process per host core (at most 16, the box's share) on a grid of
+    windows around the centre, run at once.  Runs before the GPU is touched: the
+    workers are forked."""
+    import multiprocessing as mp
+    global _CPU_SCENE
+    _CPU_SCENE = scene
     cam = scene.cameras[0]
-    side = 48
     cx, cy = cam.width // 2, cam.height // 2
-    rng = np.random.default_rng(0)
-    total_pairs, total_s = 0, 0.0
+    side = 48
     while True:
         win = (cx - side // 2, cy - side // 2, cx + side // 2, cy + side // 2)
-        t0 = time.perf_counter()
-        r = O.render(scene.params, scene.sigma, scene.background, cam, window=win)
-        g = np.zeros((3, cam.height, cam.width))
-        g[:, win[1]:win[3], win[0]:win[2]] = rng.normal(size=(3, side, side))
-        O.backward(scene.params, scene.sigma, scene.background, cam, g, window=win)
-        dt = time.perf_counter() - t0
-        total_pairs, total_s = r["pairs"], dt
-        log(f"cpu oracle: window {side}x{side}: {r['pairs']:.3e} pairs, {dt:.2f} s")
-        if dt > budget_s / 2 or side >= min(512, cam.width, cam.height) - 1:
+        pairs1, dt1 = _oracle_window(win)
+        log(f"cpu oracle, 1 core: window {side}x{side}: {pairs1:.3e} pairs, {dt1:.2f} s")
+        if dt1 > budget_s / 2 or side >= min(512, cam.width, cam.height) - 1:
             break
         # the work grows with the window area; aim the next window at the budget
-        side = min(512, cam.width, cam.height, int(side * math.sqrt(budget_s / max(dt, 1e-3))))
+        side = min(512, cam.width, cam.height, int(side * math.sqrt(budget_s / max(dt1, 1e-3))))
         side -= side % 2
-    return {"value": total_pairs / total_s, "unit": "splat-pixel evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle fwd+bwd, view 0 ({cam.width}x{cam.height}), all "
-                      f"{scene.n} splats, centre window {side}x{side}: {total_pairs} contributing pairs "
-                      f"in {total_s:.2f} s"}
+    single = {"value": pairs1 / dt1, "cores": 1,
+              "sample": f"centre window {side}x{side}: {pairs1} contributing pairs in {dt1:.2f} s"}
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    cols = math.ceil(math.sqrt(cores))
+    rows = math.ceil(cores / cols)
+    ps = min(side, cam.width // cols, cam.height // rows)
+    ps -= ps % 2
+    gx0, gy0 = cx - cols * ps // 2, cy - rows * ps // 2
+    wins = [(gx0 + (i % cols) * ps, gy0 + (i // cols) * ps, gx0 + (i % cols + 1) * ps, gy0 + (i // cols + 1) * ps)
+            for i in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_window, wins)
+    wall = time.perf_counter() - t0
+    pairs = sum(r[0] for r in res)
+    log(f"cpu oracle, {cores} cores: {cores} windows {ps}x{ps}: {pairs:.3e} pairs, {wall:.2f} s")
+    return {"value": pairs / wall, "unit": "splat-pixel evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle fwd+bwd, view 0 ({cam.width}x{cam.height}), all {scene.n} splats: "
+                      f"{cores} processes on a {cols}x{rows} grid of {ps}x{ps} windows around the centre, "
+                      f"{pairs} contributing pairs in {wall:.2f} s wall",
+            "single_core": single}
 
 
 def main():
@@ -379,6 +541,8 @@ def main():
     ap.add_argument("--densify", action="store_true",
                     help="instead of the benchmark line, time the first training phase with densification")
     ap.add_argument("--keep-probability", type=float, default=0.5, help="densification keep probability (--densify)")
+    ap.add_argument("--late-gap", type=int, default=100,
+                    help="untimed steps between the timed window and a second, later timed window (0: none)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -387,9 +551,17 @@ def main():
               f"described, not built", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2605_13855_amd import scenes
+    bench_line = not (args.ablation or args.densify or args.schedule)
+    scene = cpu = None
+    if bench_line:
+        log(f"building scene config {args.config}")
+        scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
+        # the oracle's workers are forked before anything touches the GPU
+        cpu = None if args.no_cpu else cpu_baseline(scene)
+
     import torch
     from paper_2605_13855_amd import oit  # noqa: F401  (fails loudly without the HIP library)
-    from paper_2605_13855_amd import scenes
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -428,13 +600,11 @@ def main():
                         f"~{args.fraction:.0%} active, L1 + D-SSIM", "tile": args.tile, "batch": args.batch}}),
               flush=True)
         return
-    log(f"building scene config {args.config}")
-    scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
     px = sum(c.width * c.height for c in scene.cameras)
     log(f"scene: {scene.n} splats, {len(scene.cameras)} views, {px} pixels")
 
     act = run_form(scene, False, args.steps, args.warmup, args.fraction, args.tile, args.batch,
-                   not args.no_autotune, args.eager)
+                   not args.no_autotune, args.eager, late_gap=args.late_gap)
     dense = None
     if not args.no_dense:
         dense = run_form(scene, True, max(3, args.steps // 4), max(1, args.warmup // 2), 1.0, act["tile"],
@@ -453,9 +623,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": committed_traffic(kname, act["tile"], act["batch"]),
                 "flops_per_launch": kflops, "avg_launch_ms": round(kms, 4), "timed_launches": act["kernel_steps"]}
-    cpu = None if args.no_cpu else cpu_baseline(scene)
-
     value = act["pairs"] / (act["ms_per_step"] * 1e-3)
+    nv = len(scene.cameras)
     line = {
         "metric": "fwd+bwd ms/iter and splat-pixel evals/s, active-set vs dense, 1M splats",
         "value": value,
@@ -481,6 +650,10 @@ def main():
                    "evals_per_s": value, "contributing_pairs": act["pairs"], "evaluated_pairs": act["evals"],
                    "tile_entries": act["entries"], "bwd_work_items": act["chunks"], "bwd_box_items": act["box_items"],
                    "raster_fwd_ms": round(act["raster_fwd_ms"], 4), "raster_bwd_ms": round(act["raster_bwd_ms"], 4),
+                   "label_changes_per_step": {"mean": round(statistics.mean(act["label_changes"]), 1),
+                                              "min": min(act["label_changes"]), "max": max(act["label_changes"])},
+                   "late_window": act["late"],
+                   "stages": stage_roofs(act, scene.n, nv, px, False),
                    "loss": act["loss"], "autotune": act["tuned"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -492,7 +665,14 @@ def main():
                          "tile_entries": dense["entries"], "bwd_work_items": dense["chunks"],
                          "bwd_box_items": dense["box_items"],
                          "raster_fwd_ms": round(dense["raster_fwd_ms"], 4),
-                         "raster_bwd_ms": round(dense["raster_bwd_ms"], 4)}
+                         "raster_bwd_ms": round(dense["raster_bwd_ms"], 4),
+                         "stages": stage_roofs(dense, scene.n, nv, px, True)}
+        db, dflops = step_bytes(dense, scene.n, nv, px, True)
+        rate = db / (dense["ms_per_step"] * 1e-3) / 1e9
+        line["dense"]["hbm"] = {"alg_bytes_per_step": db, "GB_s": round(rate, 1),
+                                "hbm_frac": round(rate / PEAK_HBM_GBS, 4),
+                                "alg_flops_per_step": dflops,
+                                "valu_frac": round(dflops / (dense["ms_per_step"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
         line["speedup_active_vs_dense"] = round(dense["ms_per_step"] / act["ms_per_step"], 3)
     print(json.dumps(line), flush=True)
 

@@ -458,6 +458,13 @@ oit_status oit_timing_enable(int32_t on);
  * backward raster kernel (-1 if not recorded). */
 oit_status oit_timing_read(float *out);
 
+/* Wait for the last recorded stage events; out (host) [6] = milliseconds of the last
+ * forward's preprocess, binning and raster stage (the raster kernel and its counter
+ * sum) and of the last backward's pixel constants, raster stage (work-item map and
+ * raster kernel) and preprocess backward (with the dL/dsigma sum), each measured
+ * between events recorded on the stream at the stage boundaries (-1 if not recorded). */
+oit_status oit_timing_read_stages(float *out);
+
 /* Clear the status word (enqueued on `stream`). */
 oit_status oit_clear_status(void *ws, size_t ws_bytes, oit_stream stream);
 

@@ -825,6 +825,34 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
 // the records that cannot touch its pixels.  A thread's pixels share one column, so
 // the per-column exponent terms are formed once per record.
 // ---------------------------------------------------------------------------------
+// Launch order of the forward: workgroup b runs on XCD b mod 8 and takes the tiles of
+// super-tile (b / 8 / kSupEdge^2) * 8 + b mod 8, one tile per workgroup, row by row; so
+// the kSupEdge^2 tiles of a super-tile run on one XCD, where the records that several of
+// them stage meet in the same L2, and consecutive super-tiles go to different XCDs,
+// which mixes the views and the image regions on every XCD.  Returns false for the
+// slots past a view's last tile row or column and past the last super-tile.
+constexpr int kSupTiles = kSupEdge * kSupEdge;
+
+__host__ __device__ inline unsigned fwd_grid(int n_sup)
+{
+    return (unsigned)((n_sup + kXcds - 1) / kXcds) * kXcds * kSupTiles;
+}
+
+__device__ __forceinline__ bool fwd_tile_of_block(const Buffers &b, int &v, int &tx, int &ty)
+{
+    const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
+    const int s = (k / kSupTiles) * kXcds + xcd, q = k % kSupTiles;
+    if (s >= b.n_sup) return false;
+    v = 0;
+    for (int j = 1; j < b.n_views; ++j)
+        if (s >= b.cams[j].sup_base) v = j;
+    const CamDev &cam = b.cams[v];
+    const int sl = s - cam.sup_base;
+    tx = (sl % cam.sups_x) * kSupEdge + q % kSupEdge;
+    ty = (sl / cam.sups_x) * kSupEdge + q / kSupEdge;
+    return tx < cam.tiles_x && ty < cam.tiles_y;
+}
+
 struct FwdArgs {
     Buffers b;
     const float *sigma;
@@ -861,6 +889,24 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
     return mask;
 }
 
+// Stage record r (as stage_rec) and test it against one rectangle of the tile's pixel
+// offsets, [bx, bx + w - 1] x [by, by + h - 1]: does the footprint box reach it?
+__device__ __forceinline__ bool stage_rec_rect(float4 *dst, const Rec &r, float x0, float y0, int bx, int by,
+                                               int w, int h)
+{
+    const float dx0 = x0 - r.a.x, dy0 = y0 - r.a.y;
+    dst[0] = make_float4(dx0, dy0, r.a.z, r.a.w);
+    dst[1] = r.b;
+    dst[2] = r.c;
+    const float A = -r.a.z, B = -0.5f * r.a.w, C = -r.b.x;
+    const float det = A * C - B * B;
+    const float tau = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
+    if (!(tau > 0.f && det > 0.f)) return false;
+    const float hx = sqrtf(tau * C / det) + 0.01f, hy = sqrtf(tau * A / det) + 0.01f;
+    const float rx = dx0 + (float)bx, ry = dy0 + (float)by;
+    return rx <= hx && rx + (float)(w - 1) >= -hx && ry <= hy && ry + (float)(h - 1) >= -hy;
+}
+
 // Blend-and-update one label-change record (staged at r) into a thread's PPT pixels:
 // sign-weighted, sigma-free sums (sign * alpha * v and the same times d, by colour),
 // and the factors (1 - alpha) into the product T of the record's sign.
@@ -888,7 +934,7 @@ __device__ __forceinline__ void bau_record(const float4 *r, float colf, const fl
             dP1[p][2] = fmaf(rc.x, savd, dP1[p][2]);
             dQ0[p] += sav;
             dQ1[p] += savd;
-            T[p] *= 1.f - al;
+            T[p] = fmaf(-al, T[p], T[p]);   // T (1 - alpha)
         }
     }
 }
@@ -926,24 +972,22 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
             P[p][2] = fmaf(rc.x, aw, P[p][2]);
             Q[p] += aw;
             Qs[p] = fmaf(al, rc.z, Qs[p]);
-            T[p] *= 1.f - al;
+            T[p] = fmaf(-al, T[p], T[p]);   // T (1 - alpha)
         }
     }
 }
 
-// One block per tile.  PRE (a pre-rendered buffer is given): the pixel reads the
-// inactive set's terms of the composite from it, and with BAU (the call lists label
-// changes) the label changes are first blended into it (each pixel's sign-weighted
-// deltas are added to its stored accumulators, which are written back).  Then the
-// active entries are blended (BAN) and the image and the pixel state are written.
-// Without PRE the active entries are the whole set.  With BAU at tile 32 the label
-// changes' accumulators would take 94 registers and hold the whole kernel at five waves
-// per SIMD; at six the compiler keeps them in 80, with a few reloads per batch of
-// records outside the per-record loops.  A call without a label-change list takes the
-// variant without them, which keeps the active part's eight waves.
+// One block per tile.  PRE (a pre-rendered buffer is given): the label changes (BAU,
+// when the call lists them) are first blended into the pre-rendered buffer (each
+// pixel's sign-weighted deltas are added to its stored accumulators, in passes over
+// half of a thread's pixels at tile 32), then every pixel reads the inactive set's
+// terms from it and blends the active entries on top (BAN), and the image and the
+// pixel state are written.  Without PRE the active entries are the whole set.  With
+// BAU at tile 32 the kernel takes 72 registers without spilling (seven waves per SIMD;
+// held to eight it spills 36 bytes per lane); the other variants run at eight.
 template <int S, int BATCH, bool PRE, bool BAU>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256)
-__attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(FwdArgs a)
+__attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(FwdArgs a)
 {
     static_assert(PRE || !BAU, "label changes go into a pre-rendered buffer");
     constexpr int NT = S * S < 256 ? S * S : 256;
@@ -958,11 +1002,10 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
     __shared__ float4 s_rec[kStage * 3];
     __shared__ int s_mask[BATCH];
 
-    const int tile = blockIdx.x;
-    const int v = view_of_tile(a.b.cams, a.b.n_views, tile);
+    int v, tx, ty;
+    if (!fwd_tile_of_block(a.b, v, tx, ty)) return;   // a slot past the view's last tile
     const CamDev &cam = a.b.cams[v];
-    const int lt = tile - cam.tile_base;
-    const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+    const int tile = cam.tile_base + ty * cam.tiles_x + tx;
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wbit = 1 << wave;
@@ -992,49 +1035,42 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
 
     const float sigma = *a.sigma;
     const float isig = 1.f / sigma;
-    // the inactive set's terms of the composite at each pixel (PRE): P0 - P1 / sigma,
-    // Q0 - Q1 / sigma and T = exp(log T); with BAU read here, once the label changes
-    // are added, without it read after the active entries
-    float preP[PPT][3], preQ[PPT], preT[PPT];
-    // dQ/dsigma at each pixel: Q1 / sigma^2 of the inactive set (added when the stored
-    // terms are read) plus alpha dw/dsigma of the active entries
-    float Qs[PPT];
+    // The pixel's composite sums P, Q, T and dQ/dsigma.  With a pre-rendered buffer they
+    // start from the inactive set's terms -- P0 - P1 / sigma + Q / 2 (the colour sums are
+    // stored centred on the colour offset), Q0 - Q1 / sigma, exp(log T), Q1 / sigma^2 --
+    // read before the active entries (with BAU once the label changes are added), and
+    // the active entries are blended on top: no register holds the inactive terms apart.
+    float P[PPT][3], Q[PPT], T[PPT], Qs[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        preP[p][0] = preP[p][1] = preP[p][2] = 0.f;
-        preQ[p] = 0.f;
-        preT[p] = 1.f;
+        P[p][0] = P[p][1] = P[p][2] = 0.f;
+        Q[p] = 0.f;
+        T[p] = 1.f;
         Qs[p] = 0.f;
     }
-
-    // the pixel's stored accumulators -> its inactive-set terms of the composite (the
-    // colour sums are stored centred on the colour offset: P = P0 - P1 / sigma + Q / 2)
-    auto keep_pre = [&](int p, const float (&pv)[9]) {
-        preQ[p] = pv[6] - pv[7] * isig;
+    auto take_pre = [&](int p, const float (&pv)[9]) {
+        Q[p] = pv[6] - pv[7] * isig;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) preP[p][ch] = fmaf(kColorOffset, preQ[p], pv[ch] - pv[3 + ch] * isig);
-        preT[p] = expf(pv[8]);
-        Qs[p] = fmaf(pv[7], isig * isig, Qs[p]);
+        for (int ch = 0; ch < 3; ++ch) P[p][ch] = fmaf(kColorOffset, Q[p], pv[ch] - pv[3 + ch] * isig);
+        T[p] = expf(pv[8]);
+        Qs[p] = pv[7] * (isig * isig);
     };
     // label changes: BAU accumulators (sign-weighted, sigma-free), added to the
-    // pre-rendered buffer
+    // pre-rendered buffer.  A thread's PPT pixels are taken NPASS at a time in passes
+    // over the tile's label changes (two passes of two pixels at tile 32): eleven
+    // accumulators per pixel for all four would not fit the registers of six waves per
+    // SIMD.  Pass h covers rows [h BW / NPASS, (h + 1) BW / NPASS) of the wave's block,
+    // and a record that misses those rows is skipped in that pass.
     if (BAU && nd > 0) {
+        constexpr int NPASS = PPT >= 4 ? 2 : 1;
+        constexpr int PB = PPT / NPASS;
         // log T changes by sum sign * ln(1 - alpha): the factors of each sign are
         // multiplied (Tp: +1, Tm: -1) and folded into dL every kFold records, before
         // a product of factors >= 1 - kAlphaMax can underflow
         constexpr int kFold = 16;
-        float dP0[PPT][3], dP1[PPT][3], dQ0[PPT], dQ1[PPT], dL[PPT], Tp[PPT], Tm[PPT];
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
-            dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
-            dQ0[p] = dQ1[p] = dL[p] = 0.f;
-            Tp[p] = Tm[p] = 1.f;
-        }
-        int since_fold = 0;
         // Each wave stages the tile's label changes itself, 64 at a time (one per lane),
-        // in its own LDS slice, and keeps those that reach its pixel block: the waves of
-        // a tile never wait for one another, and a wave whose block the changes miss
+        // in its own LDS slice, and keeps those that reach its pixels: the waves of a
+        // tile never wait for one another, and a wave whose pixels the changes miss
         // ends early.
         // The loads are pipelined: a batch's entry indices are read two batches ahead and
         // its records one batch ahead, so both latencies overlap the work on a batch.
@@ -1051,63 +1087,78 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
             r.c.x -= kColorOffset;
             return r;
         };
-        Rec cur = kNoRec;
-        uint32_t ri_next = 0xffffffffu;
-        if (lane < nd) cur = rec_of_entry_c(ent[lane]);
-        if (64 + lane < nd) ri_next = ent[64 + lane];
-        for (uint64_t base = 0; base < nd; base += 64) {
-            const int cnt = (int)(nd - base < 64 ? nd - base : 64);
-            int m = 0;
-            // bit 8: the record leaves the pre-rendered set's complement (sign -1)
-            if (lane < cnt) m = stage_rec<BW, WPR, NW>(&wrec[3 * lane], cur, x0, y0) | (cur.c.w < 0.f ? 0x100 : 0);
-            __builtin_amdgcn_wave_barrier();
-            // next batch's records (their indices are here), the batch after's indices
-            cur = kNoRec;
-            if (base + 64 + lane < nd) cur = rec_of_entry_c(ri_next);
-            ri_next = 0xffffffffu;
-            if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
-            const bool mine = (m & wbit) != 0;
-            uint64_t todo_p = __ballot(mine && !(m & 0x100)), todo_m = __ballot(mine && (m & 0x100));
-            // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
-            while (todo_p) {
-                const int j = (int)__builtin_ctzll(todo_p);
-                todo_p &= todo_p - 1;
-                bau_record<PPT>(wrec + 3 * j, colf, rowf, 1.f, dP0, dP1, dQ0, dQ1, Tp);
-                if (++since_fold == kFold) {
-                    since_fold = 0;
-                    fold_log_t<PPT>(dL, Tp, Tm);
+        const int bx = (wave % WPR) * BW, by = (wave / WPR) * BW;
+        // unrolled: the passes index the pixel arrays with compile-time indices
+#pragma unroll
+        for (int h = 0; h < NPASS; ++h) {
+            float rows[PB];
+#pragma unroll
+            for (int j = 0; j < PB; ++j) rows[j] = rowf[h * PB + j];
+            float dP0[PB][3], dP1[PB][3], dQ0[PB], dQ1[PB], dL[PB], Tp[PB], Tm[PB];
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                dP0[p][0] = dP0[p][1] = dP0[p][2] = 0.f;
+                dP1[p][0] = dP1[p][1] = dP1[p][2] = 0.f;
+                dQ0[p] = dQ1[p] = dL[p] = 0.f;
+                Tp[p] = Tm[p] = 1.f;
+            }
+            int since_fold = 0;
+            Rec cur = kNoRec;
+            uint32_t ri_next = 0xffffffffu;
+            if (lane < nd) cur = rec_of_entry_c(ent[lane]);
+            if (64 + lane < nd) ri_next = ent[64 + lane];
+            for (uint64_t base = 0; base < nd; base += 64) {
+                const int cnt = (int)(nd - base < 64 ? nd - base : 64);
+                bool mine = false;
+                if (lane < cnt)
+                    mine = stage_rec_rect(&wrec[3 * lane], cur, x0, y0, bx, by + h * (BW / NPASS), BW, BW / NPASS);
+                // sign -1: the record leaves the pre-rendered set's complement
+                const bool minus = cur.c.w < 0.f;
+                __builtin_amdgcn_wave_barrier();
+                // next batch's records (their indices are here), the batch after's indices
+                cur = kNoRec;
+                if (base + 64 + lane < nd) cur = rec_of_entry_c(ri_next);
+                ri_next = 0xffffffffu;
+                if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
+                uint64_t todo_p = __ballot(mine && !minus), todo_m = __ballot(mine && minus);
+                // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
+                while (todo_p) {
+                    const int j = (int)__builtin_ctzll(todo_p);
+                    todo_p &= todo_p - 1;
+                    bau_record<PB>(wrec + 3 * j, colf, rows, 1.f, dP0, dP1, dQ0, dQ1, Tp);
+                    if (++since_fold == kFold) {
+                        since_fold = 0;
+                        fold_log_t<PB>(dL, Tp, Tm);
+                    }
                 }
-            }
-            while (todo_m) {
-                const int j = (int)__builtin_ctzll(todo_m);
-                todo_m &= todo_m - 1;
-                bau_record<PPT>(wrec + 3 * j, colf, rowf, -1.f, dP0, dP1, dQ0, dQ1, Tm);
-                if (++since_fold == kFold) {
-                    since_fold = 0;
-                    fold_log_t<PPT>(dL, Tp, Tm);
+                while (todo_m) {
+                    const int j = (int)__builtin_ctzll(todo_m);
+                    todo_m &= todo_m - 1;
+                    bau_record<PB>(wrec + 3 * j, colf, rows, -1.f, dP0, dP1, dQ0, dQ1, Tm);
+                    if (++since_fold == kFold) {
+                        since_fold = 0;
+                        fold_log_t<PB>(dL, Tp, Tm);
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
-            __builtin_amdgcn_wave_barrier();
-        }
-        fold_log_t<PPT>(dL, Tp, Tm);
+            fold_log_t<PB>(dL, Tp, Tm);
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            if (!in[p]) continue;
-            const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
-            float *pr = a.pre + 9 * pb + pix;
-            const float add[9] = {dP0[p][0], dP0[p][1], dP0[p][2], dP1[p][0], dP1[p][1],
-                                  dP1[p][2], dQ0[p],    dQ1[p],    dL[p]};
-            float pv[9];
+            for (int j = 0; j < PB; ++j) {
+                const int p = h * PB + j;
+                if (!in[p]) continue;
+                const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
+                float *pr = a.pre + 9 * pb + pix;
+                const float add[9] = {dP0[j][0], dP0[j][1], dP0[j][2], dP1[j][0], dP1[j][1],
+                                      dP1[j][2], dQ0[j],    dQ1[j],    dL[j]};
 #pragma unroll
-            for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                pv[k] += add[k];
-                pr[k * HW] = pv[k];
+                for (int k = 0; k < 9; ++k) pr[k * HW] += add[k];
             }
-            keep_pre(p, pv);
         }
-    } else if (BAU) {
+    }
+    if (PRE) {
+        // the inactive set's terms, read back after the label changes (from L2: this
+        // thread has just written them), so that none is live during the passes
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (!in[p]) continue;
@@ -1116,18 +1167,11 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
             float pv[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
-            keep_pre(p, pv);
+            take_pre(p, pv);
         }
     }
 
     // active entries: BAN accumulators
-    float P[PPT][3], Q[PPT], T[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        P[p][0] = P[p][1] = P[p][2] = 0.f;
-        Q[p] = 0.f;
-        T[p] = 1.f;
-    }
     unsigned long long npair = 0;   // contributing in-image active pairs of this wave (counter)
     for (uint64_t base = 0; base < na; base += BATCH) {
         const int cnt = (int)(na - base < (uint64_t)BATCH ? na - base : (uint64_t)BATCH);
@@ -1169,23 +1213,8 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 6 : 1))) void k_raster_fwd(F
     for (int p = 0; p < PPT; ++p) {
         if (!in[p]) continue;
         const size_t pix = (size_t)(ty * S + row0 + p * RSTEP) * cam.W + tx * S + col;
-        float Pt[3] = {P[p][0], P[p][1], P[p][2]};
-        float Qt = Q[p], Tt = T[p];
-        if constexpr (PRE) {
-            if constexpr (!BAU) {
-                // without label changes the stored terms are read here, after the active
-                // entries, so that they are not live across the active loop
-                const float *pr = a.pre + 9 * pb + pix;
-                float pv[9];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) pv[k] = pr[k * HW];
-                keep_pre(p, pv);
-            }
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) Pt[ch] += preP[p][ch];
-            Qt += preQ[p];
-            Tt *= preT[p];
-        }
+        const float Pt[3] = {P[p][0], P[p][1], P[p][2]};
+        const float Qt = Q[p], Tt = T[p];
         const float iq = Qt > 0.f ? 1.f / Qt : 0.f;
         const float F0 = Pt[0] * iq, F1 = Pt[1] * iq, F2 = Pt[2] * iq;
         float *im = a.image + 3 * pb;
@@ -1215,7 +1244,7 @@ template <int S, bool PRE, bool BAU>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
-    const dim3 grid((unsigned)a.b.T), block(NT);
+    const dim3 grid(fwd_grid(a.b.n_sup)), block(NT);
     switch (batch) {
     case 32: launch_timed(k_raster_fwd<S, 32, PRE, BAU>, grid, block, s, t, a); return true;
     case 64: launch_timed(k_raster_fwd<S, 64, PRE, BAU>, grid, block, s, t, a); return true;

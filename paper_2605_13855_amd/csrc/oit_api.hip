@@ -17,9 +17,13 @@ namespace {
 
 thread_local char g_err[512] = "";
 
-// optional timing of the raster kernels (see oit_timing_enable): start/stop events of
-// the forward and of the backward
-hipEvent_t g_ev[4];
+// optional timing (see oit_timing_enable): start/stop events of the forward and of the
+// backward raster kernel (0-3), then events at the stage boundaries of the forward
+// (4-7: before the preprocess, after it, after the binning, after the raster stage) and
+// of the backward (8-11: before the pixel constants, after them, after the raster
+// stage, after the preprocess backward)
+constexpr int kTimingEvents = 12;
+hipEvent_t g_ev[kTimingEvents];
 bool g_timing_ready = false;
 bool g_timing_on = false;
 
@@ -65,7 +69,7 @@ struct Plan {
         vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, sig_part, loss_part,
         tile_cnt, total;
     uint32_t max_chunks;
-    int T;
+    int T, n_sup;
     int64_t total_px, Acap, Rcap;
     CamDev cams_host[kMaxViews];
 };
@@ -124,7 +128,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     if ((st = check_cams(cams, n_views)) != OIT_OK) return st;
     if ((st = check_tuning(tu)) != OIT_OK) return st;
     const int S = tu->tile;
-    int64_t tiles = 0, px = 0;
+    int64_t tiles = 0, px = 0, sups = 0;
     for (int v = 0; v < n_views; ++v) {
         const oit_camera &c = cams[v];
         CamDev &d = p.cams_host[v];
@@ -146,12 +150,16 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
         d.tiles_y = (c.height + S - 1) / S;
         d.tile_base = (int)tiles;
         d.pix_base = (int)px;
+        d.sup_base = (int)sups;
+        d.sups_x = (d.tiles_x + kSupEdge - 1) / kSupEdge;
+        sups += (int64_t)d.sups_x * ((d.tiles_y + kSupEdge - 1) / kSupEdge);
         tiles += (int64_t)d.tiles_x * d.tiles_y;
         px += (int64_t)c.width * c.height;
         if (tiles > (0xffffffffLL >> (kSizeBits + 1)) || px > 0x7fffffffLL / 9)
             return fail(OIT_ERR_INVALID, "batch too large: %lld tiles, %lld pixels", (long long)tiles, (long long)px);
     }
     p.T = (int)tiles;
+    p.n_sup = (int)sups;
     p.total_px = px;
     p.Acap = cap->active_capacity;
     p.Rcap = cap->active_capacity + cap->delta_capacity;
@@ -235,6 +243,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.tile_cnt = (unsigned long long *)(w + p.tile_cnt);
     b.n_views = n_views;
     b.T = p.T;
+    b.n_sup = p.n_sup;
     b.tile = tu->tile;
     b.bwd_mode = tu->bwd_mode;
     b.total_px = p.total_px;
@@ -417,12 +426,19 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
+    auto mark = [&](int k) {
+        if (g_timing_on) (void)hipEventRecord(g_ev[k], s);
+    };
+    mark(4);
     launch_preprocess_count(splat_ptrs(splats), splat_ptrs(delta_splats ? delta_splats : splats), sigma, rl, b, s);
+    mark(5);
     launch_binning(rl, b, s);
+    mark(6);
     const KTimer fwd_t{g_ev[0], g_ev[1]};
     if (!launch_raster_fwd(b, sigma, bg, pre, delta_idx != nullptr, image, pixstate, tuning->batch, s,
                            g_timing_on ? &fwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no forward kernel for tile %d batch %d", tuning->tile, tuning->batch);
+    mark(7);
     return check_launch("oit_render_fwd");
 }
 
@@ -539,11 +555,18 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     upload_cams(p.cams_host, n_views, b.cams, s);
     fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
     fill_u32(b.counters + CNT_BOX_ITEMS, 1, 0u, s);
+    auto mark = [&](int k) {
+        if (g_timing_on) (void)hipEventRecord(g_ev[k], s);
+    };
+    mark(8);
     launch_pixconst(b, sigma, bg, active_idx ? pre : nullptr, grad_image, pixstate, grad_sigma, s);
+    mark(9);
     const KTimer bwd_t{g_ev[2], g_ev[3]};
     if (!launch_raster_bwd(b, rl, s, g_timing_on ? &bwd_t : nullptr))
         return fail(OIT_ERR_INVALID, "no backward kernel for tile %d", tuning->tile);
+    mark(10);
     launch_preprocess_bwd(splat_ptrs(splats), sigma, rl, b, g, grad_sigma, score, e6, s);
+    mark(11);
     return check_launch("oit_render_bwd");
 }
 
@@ -817,7 +840,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
 oit_status oit_timing_enable(int32_t on)
 {
     if (on && !g_timing_ready) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kTimingEvents; ++k) {
             const hipError_t e = hipEventCreate(&g_ev[k]);
             if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_timing_enable: %s", hipGetErrorString(e));
         }
@@ -835,6 +858,21 @@ oit_status oit_timing_read(float *out)
         float ms = 0.f;
         hipError_t e = hipEventSynchronize(g_ev[2 * k + 1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_ev[2 * k], g_ev[2 * k + 1]);
+        out[k] = e == hipSuccess ? ms : -1.f;
+    }
+    return ok();
+}
+
+oit_status oit_timing_read_stages(float *out)
+{
+    if (!out) return fail(OIT_ERR_INVALID, "oit_timing_read_stages: NULL output");
+    if (!g_timing_ready) return fail(OIT_ERR_INVALID, "oit_timing_read_stages: timing was never enabled");
+    // consecutive boundary events of the forward (4-7) and of the backward (8-11)
+    const int pairs[6][2] = {{4, 5}, {5, 6}, {6, 7}, {8, 9}, {9, 10}, {10, 11}};
+    for (int k = 0; k < 6; ++k) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(g_ev[pairs[k][1]]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, g_ev[pairs[k][0]], g_ev[pairs[k][1]]);
         out[k] = e == hipSuccess ? ms : -1.f;
     }
     return ok();

@@ -84,6 +84,7 @@ struct Buffers {
     unsigned long long *tile_cnt;               // [T][2] contributing / evaluated active pairs per tile
     uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
+    int n_sup;                                  // super-tiles of the batch (kSupEdge^2 tiles each)
     int64_t total_px, pair_cap;
     int64_t Acap, Rcap;                         // record stride: Rcap per view
 };

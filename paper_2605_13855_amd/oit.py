@@ -96,12 +96,14 @@ def _load():
     L.oit_reset_opacity.argtypes = [P, P, P, I64, F, P]
     L.oit_timing_enable.argtypes = [I32]
     L.oit_timing_read.argtypes = [P]
+    L.oit_timing_read_stages.argtypes = [P]
     L.oit_last_error.argtypes = []
     L.oit_last_error.restype = ctypes.c_char_p
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
               L.oit_update_active_set_noalloc,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
-              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_label_delta,
+              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_timing_read_stages,
+              L.oit_label_delta,
               L.oit_fps_views, L.oit_densify_stats, L.oit_densify_plan, L.oit_densify_apply,
               L.oit_reset_opacity):
         f.restype = ctypes.c_int
@@ -304,6 +306,16 @@ def timing_read():
     out = (ctypes.c_float * 2)()
     _check(lib.oit_timing_read(out), "oit_timing_read")
     return float(out[0]), float(out[1])
+
+
+STAGES = ("preprocess", "binning", "raster_fwd", "pixconst", "raster_bwd", "preprocess_bwd")
+
+
+def timing_read_stages():
+    """Milliseconds of the last render_fwd's and render_bwd's stages (STAGES order)."""
+    out = (ctypes.c_float * 6)()
+    _check(lib.oit_timing_read_stages(out), "oit_timing_read_stages")
+    return dict(zip(STAGES, (float(x) for x in out)))
 
 
 def clear_status(ws, stream=None):
