@@ -230,7 +230,10 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
         r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
         r.c = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    a.b.rec[ri] = r;
+    Rec &dst = a.b.rec[ri];   // the padding is left unwritten
+    dst.a = r.a;
+    dst.b = r.b;
+    dst.c = r.c;
     a.b.rect[ri] = rect;
     a.b.nhits[pv] = hits;
 }
@@ -889,21 +892,17 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
     return mask;
 }
 
-// Stage record r (as stage_rec) and test it against one rectangle of the tile's pixel
-// offsets, [bx, bx + w - 1] x [by, by + h - 1]: does the footprint box reach it?
-__device__ __forceinline__ bool stage_rec_rect(float4 *dst, const Rec &r, float x0, float y0, int bx, int by,
-                                               int w, int h)
+// Does the footprint box of a staged record (st[0] = (x0 - mx, y0 - my, qa, qb),
+// st[1] = (qc, lo, ...)) reach the rectangle [bx, bx + w - 1] x [by, by + h - 1] of the
+// tile's pixel offsets?
+__device__ __forceinline__ bool staged_hits_rect(const float4 &s0, const float4 &s1, int bx, int by, int w, int h)
 {
-    const float dx0 = x0 - r.a.x, dy0 = y0 - r.a.y;
-    dst[0] = make_float4(dx0, dy0, r.a.z, r.a.w);
-    dst[1] = r.b;
-    dst[2] = r.c;
-    const float A = -r.a.z, B = -0.5f * r.a.w, C = -r.b.x;
+    const float A = -s0.z, B = -0.5f * s0.w, C = -s1.x;
     const float det = A * C - B * B;
-    const float tau = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
+    const float tau = (s1.y - kLog2AlphaMin) * 1.001f + 1e-3f;
     if (!(tau > 0.f && det > 0.f)) return false;
     const float hx = sqrtf(tau * C / det) + 0.01f, hy = sqrtf(tau * A / det) + 0.01f;
-    const float rx = dx0 + (float)bx, ry = dy0 + (float)by;
+    const float rx = s0.x + (float)bx, ry = s0.y + (float)by;
     return rx <= hx && rx + (float)(w - 1) >= -hx && ry <= hy && ry + (float)(h - 1) >= -hy;
 }
 
@@ -1103,23 +1102,36 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
                 Tp[p] = Tm[p] = 1.f;
             }
             int since_fold = 0;
+            // a tile's label changes that fit one batch stay staged for the second pass
+            const bool stage = h == 0 || nd > 64;
             Rec cur = kNoRec;
             uint32_t ri_next = 0xffffffffu;
-            if (lane < nd) cur = rec_of_entry_c(ent[lane]);
-            if (64 + lane < nd) ri_next = ent[64 + lane];
+            if (stage) {
+                if (lane < nd) cur = rec_of_entry_c(ent[lane]);
+                if (64 + lane < nd) ri_next = ent[64 + lane];
+            }
             for (uint64_t base = 0; base < nd; base += 64) {
                 const int cnt = (int)(nd - base < 64 ? nd - base : 64);
-                bool mine = false;
-                if (lane < cnt)
-                    mine = stage_rec_rect(&wrec[3 * lane], cur, x0, y0, bx, by + h * (BW / NPASS), BW, BW / NPASS);
-                // sign -1: the record leaves the pre-rendered set's complement
-                const bool minus = cur.c.w < 0.f;
-                __builtin_amdgcn_wave_barrier();
-                // next batch's records (their indices are here), the batch after's indices
-                cur = kNoRec;
-                if (base + 64 + lane < nd) cur = rec_of_entry_c(ri_next);
-                ri_next = 0xffffffffu;
-                if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
+                if (stage) {
+                    if (lane < cnt) {
+                        wrec[3 * lane] = make_float4(x0 - cur.a.x, y0 - cur.a.y, cur.a.z, cur.a.w);
+                        wrec[3 * lane + 1] = cur.b;
+                        wrec[3 * lane + 2] = cur.c;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    // next batch's records (their indices are here), the batch after's indices
+                    cur = kNoRec;
+                    if (base + 64 + lane < nd) cur = rec_of_entry_c(ri_next);
+                    ri_next = 0xffffffffu;
+                    if (base + 128 + lane < nd) ri_next = ent[base + 128 + lane];
+                }
+                bool mine = false, minus = false;
+                if (lane < cnt) {
+                    const float4 s0 = wrec[3 * lane], s1 = wrec[3 * lane + 1];
+                    mine = staged_hits_rect(s0, s1, bx, by + h * (BW / NPASS), BW, BW / NPASS);
+                    // sign -1: the record leaves the pre-rendered set's complement
+                    minus = wrec[3 * lane + 2].w < 0.f;
+                }
                 uint64_t todo_p = __ballot(mine && !minus), todo_m = __ballot(mine && minus);
                 // sign +1: the factors (1 - alpha) go to Tp; sign -1: to Tm and v enters negated
                 while (todo_p) {
@@ -1157,8 +1169,9 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
         }
     }
     if (PRE) {
-        // the inactive set's terms, read back after the label changes (from L2: this
-        // thread has just written them), so that none is live during the passes
+        // the inactive set's terms, read back after the label changes (this thread has
+        // just written them), so that none is live during the passes (holding the last
+        // pass's in registers instead spilled 12 bytes per lane)
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             if (!in[p]) continue;

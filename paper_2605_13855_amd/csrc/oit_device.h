@@ -50,12 +50,16 @@ struct CamDev {
 // blocks then request the same lines at once).
 constexpr int kSupEdge = 2;
 
-// Record of one (view, listed splat), 3 x float4 = 48 bytes, read by the rasterisers.
+// Record of one (view, listed splat), 3 x float4 = 48 bytes used, read by the
+// rasterisers, padded to 64 bytes: a record is gathered alone (its tile's list orders
+// the records by tile, not by address), and at a 64-byte stride it takes one memory
+// sector instead of one or two.
 //   a = (mx, my, qa, qb)   b = (qc, lo, c_r, c_g)   c = (c_b, wv, dd, sgn)
 // active records: wv = w,  dd = dw/dsigma (0 when d >= sigma),  sgn = 1
 // label-change records: wv = v (0 when d >= sigma), dd = d, sgn = -1 (leaves pre) / +1
 struct Rec {
     float4 a, b, c;
+    float4 pad;   // never written or read
 };
 
 // ---------------------------------------------------------------------------------
