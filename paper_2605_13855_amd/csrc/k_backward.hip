@@ -741,14 +741,15 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
         const uint64_t n = g0 >= cap ? 0 : (nh < cap - g0 ? nh : cap - g0);
         // rows four at a time: the loads are issued together, the sums stay in row order
         for (uint64_t k = 0; k < n; k += 4) {
-            float4 e0[4], e1[4], e2[4];
+            float4 e0[4], e1[4];
+            float3 e2[4];   // the row's last three partials (the fourth float is padding)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (k + j < n) {
                     const float *e = a.b.ep + (g0 + k + j) * kEpStride;
                     e0[j] = ((const float4 *)e)[0];
                     e1[j] = ((const float4 *)e)[1];
-                    e2[j] = ((const float4 *)e)[2];
+                    e2[j] = make_float3(e[8], e[9], e[10]);
                 }
             }
 #pragma unroll
@@ -810,9 +811,10 @@ __device__ void view_partials(const PreBwdArgs &a, int64_t nrec, int64_t t, int6
         if (tz < sigma) {
             const float gv = gw * (1.f - tz / sigma);
             g_tc[2] += -gw * vv / sigma;
-            // sum over the pixels of alpha (A.c - s1) (dw/dsigma - lambda w)
-            const double sd = (double)sigma, vd = (double)vv, zd = (double)tz;
-            o.gsig = (double)gw * vd * zd / (sd * sd) - (double)gs[10] * vd * (1.0 - zd / sd);
+            // sum over the pixels of alpha (A.c - s1) (dw/dsigma - lambda w): dw/dsigma and
+            // w in float, as the forward pass forms them; the difference in double
+            const float dw = vv * tz / (sigma * sigma), wv = (1.f - tz / sigma) * vv;
+            o.gsig = fma((double)gw, (double)dw, -(double)gs[10] * (double)wv);
             if (raw > 0.f) {
                 o.gvm = gv;
 #pragma unroll
