@@ -329,6 +329,45 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     return out
 
 
+def tile_skew(scene, fraction, tile, batch, steps):
+    """Entries per tile of the forward (one workgroup per tile): per view the mean and
+    the largest count, for the active form after `steps` training steps (active entries
+    and label changes) and for the dense form; and the bound that the heaviest tile puts
+    on a launch's tail, max / (total / resident workgroups)."""
+    import numpy as np
+    import torch
+    from paper_2605_13855_amd.render import ActiveSetTrainer
+    out = {}
+    for name, dense in (("active", False), ("dense", True)):
+        t = ActiveSetTrainer(scene, fraction=fraction, tile=tile, batch=batch, dense=dense)
+        if not dense:
+            t.warmup_dense_scores()
+        need = prime(t)
+        t.r.set_tuning(pair_capacity=min(int(need * 1.5) + 65536, 2 ** 32 - 2))
+        for _ in range(steps if not dense else 1):
+            t.iteration()
+        torch.cuda.synchronize()
+        views = t.r.tile_entries()
+        per_view, allw = [], []
+        for k, v in enumerate(views):
+            a, d = v[0].astype(np.float64), v[1].astype(np.float64)
+            w = a + d
+            allw.append(w.ravel())
+            per_view.append({"view": k, "tiles": int(w.size), "active_mean": round(float(a.mean()), 1),
+                             "active_max": int(a.max()), "changes_mean": round(float(d.mean()), 1),
+                             "changes_max": int(d.max()), "max_over_mean": round(float(w.max() / max(w.mean(), 1e-9)), 2)})
+        w = np.concatenate(allw)
+        resident = 256 * 7   # workgroups of the forward at tile 32 (seven waves per SIMD, four per block)
+        out[name] = {"views": per_view, "tiles": int(w.size), "entries": int(w.sum()),
+                     "mean": round(float(w.mean()), 1), "max": int(w.max()),
+                     "max_over_mean": round(float(w.max() / max(w.mean(), 1e-9)), 2),
+                     "tail_bound": round(float(w.max() / max(w.sum() / resident, 1e-9)), 3)}
+        log(f"tile skew {name}: mean {out[name]['mean']}, max {out[name]['max']}, tail bound {out[name]['tail_bound']}")
+        del t
+        torch.cuda.empty_cache()
+    return out
+
+
 def ablation(scene, steps, tile, batch):
     """Synthetic analogue of the paper's backward ablation (Tab. "ablation"): the dense
     iteration with the per-splat backward against the per-pixel backward that adds an
@@ -541,6 +580,8 @@ def main():
     ap.add_argument("--densify", action="store_true",
                     help="instead of the benchmark line, time the first training phase with densification")
     ap.add_argument("--keep-probability", type=float, default=0.5, help="densification keep probability (--densify)")
+    ap.add_argument("--tile-skew", action="store_true",
+                    help="instead of the benchmark line, report the forward's entries per tile (active and dense)")
     ap.add_argument("--late-gap", type=int, default=100,
                     help="untimed steps between the timed window and a second, later timed window (0: none)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -552,7 +593,7 @@ def main():
         sys.exit(2)
 
     from paper_2605_13855_amd import scenes
-    bench_line = not (args.ablation or args.densify or args.schedule)
+    bench_line = not (args.ablation or args.densify or args.schedule or args.tile_skew)
     scene = cpu = None
     if bench_line:
         log(f"building scene config {args.config}")
@@ -580,6 +621,14 @@ def main():
         res = ablation(scene, args.steps, args.tile, args.batch)
         print(json.dumps({"ablation": res, "config": {"workload": f"config {cfg}: {scene.n} splats, "
                           f"{len(scene.cameras)} view(s), dense fwd+bwd, L1"}}), flush=True)
+        return
+    if args.tile_skew:
+        scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)
+        res = tile_skew(scene, args.fraction, args.tile, args.batch, args.steps)
+        print(json.dumps({"tile_skew": res, "config": {
+            "workload": f"config {args.config}: {scene.n} splats, {len(scene.cameras)} views, "
+                        f"{args.fraction:.0%} active after {args.steps} steps; dense",
+            "tile": args.tile, "batch": args.batch}}), flush=True)
         return
     if args.densify:
         scene = scenes.make_scene(args.config, log_scale_mu=args.log_scale_mu)

@@ -442,6 +442,18 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
                              int64_t *out, oit_stream stream);
 
 /*
+ * Wait for `stream` and copy the per-tile entry counts of the last oit_render_fwd on
+ * this workspace (arguments as given to that call): out (host) [2][T], T = the tiles
+ * of the batch (views in order, each row-major, ceil(W / tile) x ceil(H / tile)); row 0
+ * holds each tile's active entries, row 1 its label-change entries.  out_len is the
+ * length of out in elements (at least 2 T, else OIT_ERR_INVALID).  A diagnostic of the
+ * work per tile (the forward runs one workgroup per tile).
+ */
+oit_status oit_read_tile_entries(const void *ws, size_t ws_bytes, const oit_capacity *cap,
+                                 const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,
+                                 uint32_t *out, int64_t out_len, oit_stream stream);
+
+/*
  * Timing of the raster kernels, for benchmarks.  While enabled (on != 0), every
  * oit_render_fwd launches its raster kernel (label changes into `pre`, when given,
  * then the active entries, in one launch) and every oit_render_bwd its raster kernel with HIP

@@ -342,9 +342,41 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
     }
 }
 
+// The forward's launch order: the tiles by decreasing entry count (a quarter-octave
+// bucket of the count; any order within a bucket), so that the heaviest tiles start
+// first and the launch ends on light ones (longest-first list scheduling; the largest
+// tile holds about 2.7 times the mean at config 4).  One block; the order within a
+// bucket follows LDS atomics and changes no result (each tile is independent).
+constexpr int kOrderBuckets = 128;
+
+__global__ __launch_bounds__(1024) void k_tile_order(Buffers b)
+{
+    __shared__ uint32_t s_n[kOrderBuckets], s_pos[kOrderBuckets];
+    const int T = b.T;
+    auto bucket = [&](int t) {
+        const uint32_t w = b.cnt_a[t] + b.cnt_d[t];
+        const int q = (int)(4.f * __builtin_amdgcn_logf((float)w + 1.f));   // log2 of the count, x 4
+        return kOrderBuckets - 1 - min(q, kOrderBuckets - 1);                // heaviest first
+    };
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x) s_n[k] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += blockDim.x) atomicAdd(&s_n[bucket(t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < kOrderBuckets; ++k) {
+            s_pos[k] = acc;
+            acc += s_n[k];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += blockDim.x) b.tile_order[atomicAdd(&s_pos[bucket(t)], 1u)] = (uint32_t)t;
+}
+
 void launch_scan_tiles(const Buffers &b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, b);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, b);
 }
 
 // ---------------------------------------------------------------------------------
@@ -828,32 +860,15 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
 // the records that cannot touch its pixels.  A thread's pixels share one column, so
 // the per-column exponent terms are formed once per record.
 // ---------------------------------------------------------------------------------
-// Launch order of the forward: workgroup b runs on XCD b mod 8 and takes the tiles of
-// super-tile (b / 8 / kSupEdge^2) * 8 + b mod 8, one tile per workgroup, row by row; so
-// the kSupEdge^2 tiles of a super-tile run on one XCD, where the records that several of
-// them stage meet in the same L2, and consecutive super-tiles go to different XCDs,
-// which mixes the views and the image regions on every XCD.  Returns false for the
-// slots past a view's last tile row or column and past the last super-tile.
-constexpr int kSupTiles = kSupEdge * kSupEdge;
-
-__host__ __device__ inline unsigned fwd_grid(int n_sup)
+// The forward's workgroup b takes the b-th tile of the heavy-first order (k_tile_order).
+__device__ __forceinline__ void fwd_tile_of_block(const Buffers &b, int &v, int &tx, int &ty)
 {
-    return (unsigned)((n_sup + kXcds - 1) / kXcds) * kXcds * kSupTiles;
-}
-
-__device__ __forceinline__ bool fwd_tile_of_block(const Buffers &b, int &v, int &tx, int &ty)
-{
-    const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
-    const int s = (k / kSupTiles) * kXcds + xcd, q = k % kSupTiles;
-    if (s >= b.n_sup) return false;
-    v = 0;
-    for (int j = 1; j < b.n_views; ++j)
-        if (s >= b.cams[j].sup_base) v = j;
+    const int tile = (int)b.tile_order[blockIdx.x];
+    v = view_of_tile(b.cams, b.n_views, tile);
     const CamDev &cam = b.cams[v];
-    const int sl = s - cam.sup_base;
-    tx = (sl % cam.sups_x) * kSupEdge + q % kSupEdge;
-    ty = (sl / cam.sups_x) * kSupEdge + q / kSupEdge;
-    return tx < cam.tiles_x && ty < cam.tiles_y;
+    const int lt = tile - cam.tile_base;
+    tx = lt % cam.tiles_x;
+    ty = lt / cam.tiles_x;
 }
 
 struct FwdArgs {
@@ -1002,7 +1017,7 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
     __shared__ int s_mask[BATCH];
 
     int v, tx, ty;
-    if (!fwd_tile_of_block(a.b, v, tx, ty)) return;   // a slot past the view's last tile
+    fwd_tile_of_block(a.b, v, tx, ty);
     const CamDev &cam = a.b.cams[v];
     const int tile = cam.tile_base + ty * cam.tiles_x + tx;
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
@@ -1257,7 +1272,7 @@ template <int S, bool PRE, bool BAU>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
     constexpr int NT = S * S < 256 ? S * S : 256;
-    const dim3 grid(fwd_grid(a.b.n_sup)), block(NT);
+    const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
     case 32: launch_timed(k_raster_fwd<S, 32, PRE, BAU>, grid, block, s, t, a); return true;
     case 64: launch_timed(k_raster_fwd<S, 64, PRE, BAU>, grid, block, s, t, a); return true;

@@ -65,11 +65,11 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 struct Plan {
-    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, entries, orig, keys0, keys1, vals0,
+    size_t status, cams, counters, tiles, tile_off, chunk_off, chunk_tile, tile_order, entries, orig, keys0, keys1, vals0,
         vals1, recs0, recs1, hist, hist_off, rec, rect, nhits, hoff, scan_tmp, ep, pixconst, pixB, sig_part, loss_part,
         tile_cnt, total;
     uint32_t max_chunks;
-    int T, n_sup;
+    int T;
     int64_t total_px, Acap, Rcap;
     CamDev cams_host[kMaxViews];
 };
@@ -128,7 +128,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     if ((st = check_cams(cams, n_views)) != OIT_OK) return st;
     if ((st = check_tuning(tu)) != OIT_OK) return st;
     const int S = tu->tile;
-    int64_t tiles = 0, px = 0, sups = 0;
+    int64_t tiles = 0, px = 0;
     for (int v = 0; v < n_views; ++v) {
         const oit_camera &c = cams[v];
         CamDev &d = p.cams_host[v];
@@ -150,16 +150,12 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
         d.tiles_y = (c.height + S - 1) / S;
         d.tile_base = (int)tiles;
         d.pix_base = (int)px;
-        d.sup_base = (int)sups;
-        d.sups_x = (d.tiles_x + kSupEdge - 1) / kSupEdge;
-        sups += (int64_t)d.sups_x * ((d.tiles_y + kSupEdge - 1) / kSupEdge);
         tiles += (int64_t)d.tiles_x * d.tiles_y;
         px += (int64_t)c.width * c.height;
         if (tiles > (0xffffffffLL >> (kSizeBits + 1)) || px > 0x7fffffffLL / 9)
             return fail(OIT_ERR_INVALID, "batch too large: %lld tiles, %lld pixels", (long long)tiles, (long long)px);
     }
     p.T = (int)tiles;
-    p.n_sup = (int)sups;
     p.total_px = px;
     p.Acap = cap->active_capacity;
     p.Rcap = cap->active_capacity + cap->delta_capacity;
@@ -172,6 +168,7 @@ oit_status make_plan(const oit_capacity *cap, const oit_camera *cams, int32_t n_
     p.tiles = o; o = align256(o + 4 * 2 * (size_t)p.T);
     p.tile_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
     p.chunk_off = o; o = align256(o + 4 * ((size_t)p.T + 1));
+    p.tile_order = o; o = align256(o + 4 * (size_t)p.T);
     // every tile adds at most one partial chunk to the pair capacity's full ones
     const uint64_t mc = (uint64_t)tu->pair_capacity / kBwdLanes + (uint64_t)p.T + 1;
     p.max_chunks = (uint32_t)(mc < 0xffffffffull ? mc : 0xffffffffull);
@@ -219,6 +216,7 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.tile_off = (uint32_t *)(w + p.tile_off);
     b.chunk_off = (uint32_t *)(w + p.chunk_off);
     b.chunk_tile = (uint32_t *)(w + p.chunk_tile);
+    b.tile_order = (uint32_t *)(w + p.tile_order);
     b.max_chunks = p.max_chunks;
     b.entries = (uint32_t *)(w + p.entries);
     b.orig = (uint32_t *)(w + p.orig);
@@ -243,7 +241,6 @@ Buffers buffers(const Plan &p, void *ws, int n_views, const oit_tuning *tu)
     b.tile_cnt = (unsigned long long *)(w + p.tile_cnt);
     b.n_views = n_views;
     b.T = p.T;
-    b.n_sup = p.n_sup;
     b.tile = tu->tile;
     b.bwd_mode = tu->bwd_mode;
     b.total_px = p.total_px;
@@ -834,6 +831,23 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
     out[2] = (int64_t)((uint64_t)v[CNT_EVAL] | ((uint64_t)v[CNT_EVAL + 1] << 32));
     out[3] = (int64_t)v[CNT_TOTAL_CHUNKS];
     out[4] = (int64_t)v[CNT_BOX_ITEMS];
+    return ok();
+}
+
+oit_status oit_read_tile_entries(const void *ws, size_t ws_bytes, const oit_capacity *cap, const oit_camera *cams,
+                                 int32_t n_views, const oit_tuning *tuning, uint32_t *out, int64_t out_len,
+                                 oit_stream stream)
+{
+    Plan p;
+    oit_status st;
+    if ((st = make_plan(cap, cams, n_views, tuning, p)) != OIT_OK) return st;
+    if (!ws || !out || ws_bytes < p.total || out_len < 2 * (int64_t)p.T)
+        return fail(OIT_ERR_INVALID, "oit_read_tile_entries: bad arguments");
+    // active counts then label-change counts, contiguous in the workspace
+    hipError_t e = hipMemcpyAsync(out, (const char *)ws + p.tiles, 4 * 2 * (size_t)p.T, hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail(OIT_ERR_HIP, "oit_read_tile_entries: %s", hipGetErrorString(e));
     return ok();
 }
 

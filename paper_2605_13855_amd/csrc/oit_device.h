@@ -40,15 +40,8 @@ struct CamDev {
     int tiles_x, tiles_y;
     int tile_base;    // first tile of this view in the batch
     int pix_base;     // first pixel of this view in the batch
-    int sup_base;     // first super-tile (kSupEdge x kSupEdge tiles) of this view in the batch
-    int sups_x;       // super-tiles per row
+    int pad[2];
 };
-
-// Super-tiles: the forward's launch order groups the tiles kSupEdge x kSupEdge, each
-// group on one XCD, so that the blocks that stage a splat's record for neighbouring
-// tiles share an L2 (2 x 2: 4 x 4 groups fetched less but ran 4% slower, as sixteen
-// blocks then request the same lines at once).
-constexpr int kSupEdge = 2;
 
 // Record of one (view, listed splat), 3 x float4 = 48 bytes used, read by the
 // rasterisers, padded to 64 bytes: a record is gathered alone (its tile's list orders

@@ -62,6 +62,7 @@ struct Buffers {
     uint32_t *cnt_a, *cnt_d;                    // [T] active / label-change entries per tile
     uint32_t *tile_off, *chunk_off;             // [T + 1]
     uint32_t *chunk_tile;                       // [max_chunks] tile of each backward work item
+    uint32_t *tile_order;                       // [T] the forward's launch order: heaviest tiles first
     // Tile entries.  Every (listed record, view) pair -- index view * nrec + k for the
     // k-th listed record, nrec = listed records of the call -- owns the slots
     // [hoff, hoff + nhits) of the unsorted list, one per tile it reaches; the list is
@@ -84,7 +85,6 @@ struct Buffers {
     unsigned long long *tile_cnt;               // [T][2] contributing / evaluated active pairs per tile
     uint32_t max_chunks;
     int n_views, T, tile, bwd_mode;
-    int n_sup;                                  // super-tiles of the batch (kSupEdge^2 tiles each)
     int64_t total_px, pair_cap;
     int64_t Acap, Rcap;                         // record stride: Rcap per view
 };

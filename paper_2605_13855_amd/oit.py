@@ -96,13 +96,15 @@ def _load():
     L.oit_reset_opacity.argtypes = [P, P, P, I64, F, P]
     L.oit_timing_enable.argtypes = [I32]
     L.oit_timing_read.argtypes = [P]
+    L.oit_read_tile_entries.argtypes = [P, SZ, P, P, I32, P, P, I64, P]
     L.oit_timing_read_stages.argtypes = [P]
     L.oit_last_error.argtypes = []
     L.oit_last_error.restype = ctypes.c_char_p
     for f in (L.oit_render_fwd, L.oit_l1_loss, L.oit_render_bwd, L.oit_update_active_set,
               L.oit_update_active_set_noalloc,
               L.oit_sparse_adam_step, L.oit_sigma_adam_step, L.oit_read_status, L.oit_clear_status,
-              L.oit_read_counters, L.oit_timing_enable, L.oit_timing_read, L.oit_timing_read_stages,
+              L.oit_read_counters, L.oit_read_tile_entries, L.oit_timing_enable, L.oit_timing_read,
+              L.oit_timing_read_stages,
               L.oit_label_delta,
               L.oit_fps_views, L.oit_densify_stats, L.oit_densify_plan, L.oit_densify_apply,
               L.oit_reset_opacity):
@@ -296,6 +298,17 @@ def read_counters(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, stream=N
                                out, _stream(stream))
     _check(rc, "oit_read_counters")
     return tuple(int(x) for x in out)
+
+
+def read_tile_entries(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, n_tiles: int, stream=None):
+    """Per-tile (active, label-change) entry counts of the last forward: numpy [2][T]."""
+    import numpy as np
+    out = np.zeros(2 * n_tiles, dtype=np.uint32)
+    rc = lib.oit_read_tile_entries(_ptr(ws), ws.numel(), ctypes.byref(cap), cams_arr, n_views,
+                                   ctypes.byref(tuning), out.ctypes.data_as(ctypes.c_void_p), out.size,
+                                   _stream(stream))
+    _check(rc, "oit_read_tile_entries")
+    return out.reshape(2, n_tiles)
 
 
 def timing_enable(on: bool):

@@ -147,6 +147,19 @@ class Renderer:
     def counters(self):
         return oit.read_counters(self.ws, self.cap, self.cams_arr, self.n_views, self.tuning)
 
+    def tile_entries(self):
+        """Per view, the (active, label-change) entry counts of each tile of the last
+        forward: a list of [2][tiles_y][tiles_x] numpy arrays."""
+        S = self.tuning.tile
+        shapes = [((c.height + S - 1) // S, (c.width + S - 1) // S) for c in self.cams]
+        n_tiles = sum(ty * tx for ty, tx in shapes)
+        flat = oit.read_tile_entries(self.ws, self.cap, self.cams_arr, self.n_views, self.tuning, n_tiles)
+        out, o = [], 0
+        for ty, tx in shapes:
+            out.append(flat[:, o:o + ty * tx].reshape(2, ty, tx))
+            o += ty * tx
+        return out
+
     def pairs_needed(self) -> int:
         return self.counters()[0]
 

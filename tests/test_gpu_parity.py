@@ -558,6 +558,38 @@ def test_active_set_render_equals_dense(tile, batch):
         assert err <= IMAGE_RTOL
 
 
+def test_tile_entry_counts_add_up():
+    """The per-tile entry counts (a diagnostic of the forward's work per workgroup) add up
+    to the entries the binning produced, in the active and the label-change class; in
+    dense mode no tile holds a label change."""
+    sc = scenes.random_scene(41, 3000, 96, 72, n_views=3, mean_range=1.0)
+    params = params_to_device(sc.params)
+    sigma = torch.tensor([sc.sigma], device=DEV)
+    r = Renderer(sc.cameras, sc.n, tile=16)
+    r.fit_pair_capacity(params, sigma, sc.background)
+    r.forward(params, sigma, sc.background)
+    torch.cuda.synchronize()
+    views = r.tile_entries()
+    assert [v.shape[1:] for v in views] == [((c.height + 15) // 16, (c.width + 15) // 16) for c in sc.cameras]
+    assert sum(int(v[0].sum()) for v in views) == r.pairs_needed()
+    assert all(int(v[1].sum()) == 0 for v in views)
+    k = 700
+    idx, didx, dsg, _ = run_select(torch.rand(sc.n, device=DEV), torch.ones(sc.n, dtype=torch.uint8, device=DEV), k)
+    act = {"idx": torch.tensor(idx, dtype=torch.int32, device=DEV),
+           "n": torch.tensor([len(idx)], dtype=torch.int32, device=DEV),
+           "delta_idx": torch.tensor(didx, dtype=torch.int32, device=DEV),
+           "delta_sign": torch.tensor(dsg, dtype=torch.int8, device=DEV),
+           "n_delta": torch.tensor([len(didx)], dtype=torch.int32, device=DEV)}
+    pre = torch.zeros(9 * r_total_px(sc), device=DEV)
+    ra = Renderer(sc.cameras, sc.n, active_capacity=k, delta_capacity=len(didx), tile=16)
+    ra.fit_pair_capacity(params, sigma, sc.background, act, pre)
+    ra.forward(params, sigma, sc.background, act, pre)
+    torch.cuda.synchronize()
+    views = ra.tile_entries()
+    na, nd = sum(int(v[0].sum()) for v in views), sum(int(v[1].sum()) for v in views)
+    assert na + nd == ra.pairs_needed() and na > 0 and nd > 0
+
+
 def test_pair_overflow_is_reported_and_bounded():
     sc = scenes.make_scene(1)
     params = params_to_device(sc.params)
