@@ -9,9 +9,13 @@ namespace oit {
 // ---------------------------------------------------------------------------------
 // small utilities
 // ---------------------------------------------------------------------------------
+// Cameras travel as kernel arguments (graph capture records them by value); 24 of
+// them (2.9 KB) per launch, below the kernel-argument limit.
+constexpr int kCamChunk = 24;
 struct CamChunk {
-    CamDev c[8];
+    CamDev c[kCamChunk];
 };
+static_assert(sizeof(CamChunk) <= 3584, "cameras of one upload fit the kernel arguments");
 
 __global__ void k_upload_cams(CamChunk chunk, int n, CamDev *dst)
 {
@@ -21,9 +25,9 @@ __global__ void k_upload_cams(CamChunk chunk, int n, CamDev *dst)
 
 void upload_cams(const CamDev *host, int n_views, CamDev *dst, hipStream_t s)
 {
-    for (int base = 0; base < n_views; base += 8) {
+    for (int base = 0; base < n_views; base += kCamChunk) {
         CamChunk ch;
-        const int k = n_views - base < 8 ? n_views - base : 8;
+        const int k = n_views - base < kCamChunk ? n_views - base : kCamChunk;
         for (int i = 0; i < k; ++i) ch.c[i] = host[base + i];
         hipLaunchKernelGGL(k_upload_cams, dim3(1), dim3(64), 0, s, ch, k, dst + base);
     }
@@ -270,8 +274,8 @@ void launch_preprocess_count(const SplatPtrs &sp, const SplatPtrs &dsp, const fl
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
 {
-    __shared__ unsigned long long s_e[kScanThreads];
-    __shared__ unsigned long long s_c[kScanThreads];
+    __shared__ unsigned long long s_e[kScanThreads / 64];
+    __shared__ unsigned long long s_c[kScanThreads / 64];
     const int T = b.T;
     const int tid = threadIdx.x;
     const int seg = (T + kScanThreads - 1) / kScanThreads;
@@ -301,19 +305,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
             sc += (na + kBwdLanes - 1) / kBwdLanes;
         }
     }
-    s_e[tid] = se;
-    s_c[tid] = sc;
-    __syncthreads();
-    // Hillis-Steele inclusive scan
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        unsigned long long ve = tid >= off ? s_e[tid - off] : 0ull;
-        unsigned long long vc = tid >= off ? s_c[tid - off] : 0ull;
-        __syncthreads();
-        s_e[tid] += ve;
-        s_c[tid] += vc;
-        __syncthreads();
+    // inclusive scans over each wave by shuffles, then the 16 wave totals in LDS
+    const int lane = tid & 63, wave = tid >> 6;
+    unsigned long long xe = se, xc = sc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long ye = __shfl_up(xe, o), yc = __shfl_up(xc, o);
+        if (lane >= o) {
+            xe += ye;
+            xc += yc;
+        }
     }
-    unsigned long long pe = s_e[tid] - se, pc = s_c[tid] - sc;
+    if (lane == 63) {
+        s_e[wave] = xe;
+        s_c[wave] = xc;
+    }
+    __syncthreads();
+    unsigned long long be = 0, bc = 0;
+    for (int w = 0; w < wave; ++w) {
+        be += s_e[w];
+        bc += s_c[w];
+    }
+    unsigned long long pe = be + xe - se, pc = bc + xc - sc;
     const unsigned long long cap = (unsigned long long)b.pair_cap;
     if (in_regs) {
 #pragma unroll
@@ -335,7 +347,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
         }
     }
     if (tid == kScanThreads - 1) {
-        const unsigned long long te = s_e[tid], tc = s_c[tid];
+        const unsigned long long te = be + xe, tc = bc + xc;
         b.tile_off[T] = (uint32_t)(te < cap ? te : cap);
         b.chunk_off[T] = (uint32_t)tc;
         b.counters[CNT_TOTAL_CHUNKS] = (uint32_t)tc;
@@ -729,6 +741,55 @@ __device__ __forceinline__ void sort_range(uint64_t n, uint64_t &lo, uint64_t &h
     if (lo > hi) lo = hi;
 }
 
+// Exclusive scan of the digit histograms (kRadixBuckets x kSortGrid values) in one
+// block: each thread scans 32 consecutive counts in registers, the waves' totals meet
+// in LDS (one launch instead of the three of the general scan).
+constexpr int kHistScanPer = kRadixBuckets * kSortGrid / 1024;
+static_assert(kHistScanPer == 32, "32 counts per thread");
+
+__global__ __launch_bounds__(1024) void k_scan_hist(const uint32_t *in, uint32_t *out)
+{
+    __shared__ uint32_t s_w[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint4 *src = (const uint4 *)(in + (size_t)tid * kHistScanPer);
+    uint32_t v[kHistScanPer];
+#pragma unroll
+    for (int k = 0; k < kHistScanPer / 4; ++k) {
+        const uint4 q = src[k];
+        v[4 * k] = q.x;
+        v[4 * k + 1] = q.y;
+        v[4 * k + 2] = q.z;
+        v[4 * k + 3] = q.w;
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kHistScanPer; ++k) sum += v[k];
+    uint32_t x = sum;   // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += s_w[w];
+    uint32_t pre = base + x - sum;
+    uint4 *dst = (uint4 *)(out + (size_t)tid * kHistScanPer);
+#pragma unroll
+    for (int k = 0; k < kHistScanPer / 4; ++k) {
+        uint4 q;
+        q.x = pre;
+        pre += v[4 * k];
+        q.y = pre;
+        pre += v[4 * k + 1];
+        q.z = pre;
+        pre += v[4 * k + 2];
+        q.w = pre;
+        pre += v[4 * k + 3];
+        dst[k] = q;
+    }
+}
+
 // digit histogram of each block's range, digit-major: hist[d][block]
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const uint32_t *nptr, int shift,
                                                     uint32_t *hist)
@@ -839,7 +900,7 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
         const bool last = ps == passes - 1;
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur], nptr,
                            kRadixBits * ps, b.hist);
-        launch_scan_u32(b.hist, b.hist_off, kRadixBuckets * (int64_t)kSortGrid, b.scan_tmp, s);
+        hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, s, (const uint32_t *)b.hist, b.hist_off);
         hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(256), 0, s, (const uint32_t *)b.keys[cur],
                            (const uint32_t *)b.vals[cur], (const uint32_t *)b.recs[cur], b.keys[cur ^ 1],
                            last ? b.orig : b.vals[cur ^ 1], last ? b.entries : b.recs[cur ^ 1], nptr,
