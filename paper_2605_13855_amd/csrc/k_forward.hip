@@ -359,12 +359,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(Buffers b)
 // first and the launch ends on light ones (longest-first list scheduling; the largest
 // tile holds about 2.7 times the mean at config 4).  One block; the order within a
 // bucket follows LDS atomics and changes no result (each tile is independent).
+// It also resets the forward's work-queue ticket, which the raster forward launched
+// after it on the same stream takes tiles from.
 constexpr int kOrderBuckets = 128;
 
 __global__ __launch_bounds__(1024) void k_tile_order(Buffers b)
 {
     __shared__ uint32_t s_n[kOrderBuckets], s_pos[kOrderBuckets];
     const int T = b.T;
+    if (threadIdx.x == 0) b.counters[CNT_FQUEUE] = 0u;
     auto bucket = [&](int t) {
         const uint32_t w = b.cnt_a[t] + b.cnt_d[t];
         const int q = (int)(4.f * __builtin_amdgcn_logf((float)w + 1.f));   // log2 of the count, x 4
@@ -913,7 +916,8 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------------
-// raster forward: one workgroup per tile (all views of the batch in one launch).
+// raster forward: a tile is one workgroup's work (all views of the batch in one
+// persistent launch, tiles dealt from a device queue heaviest first).
 // Records of the tile's entries are staged through LDS in batches; every thread
 // blends them into its pixels in list order (no depth order).  Each wave owns a
 // compact block of the tile (16 x 16 pixels for 32-pixel tiles, else 8 x 8), and the
@@ -921,10 +925,10 @@ void launch_binning(const RowList &rl, const Buffers &b, hipStream_t s)
 // the records that cannot touch its pixels.  A thread's pixels share one column, so
 // the per-column exponent terms are formed once per record.
 // ---------------------------------------------------------------------------------
-// The forward's workgroup b takes the b-th tile of the heavy-first order (k_tile_order).
-__device__ __forceinline__ void fwd_tile_of_block(const Buffers &b, int &v, int &tx, int &ty)
+// The tile at position k of the heavy-first order (k_tile_order).
+__device__ __forceinline__ void fwd_tile_at(const Buffers &b, uint32_t k, int &v, int &tx, int &ty)
 {
-    const int tile = (int)b.tile_order[blockIdx.x];
+    const int tile = (int)b.tile_order[k];
     v = view_of_tile(b.cams, b.n_views, tile);
     const CamDev &cam = b.cams[v];
     const int lt = tile - cam.tile_base;
@@ -1052,17 +1056,15 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
     }
 }
 
-// One block per tile.  PRE (a pre-rendered buffer is given): the label changes (BAU,
-// when the call lists them) are first blended into the pre-rendered buffer (each
-// pixel's sign-weighted deltas are added to its stored accumulators, in passes over
-// half of a thread's pixels at tile 32), then every pixel reads the inactive set's
-// terms from it and blends the active entries on top (BAN), and the image and the
-// pixel state are written.  Without PRE the active entries are the whole set.  With
-// BAU at tile 32 the kernel takes 72 registers without spilling (seven waves per SIMD;
-// held to eight it spills 36 bytes per lane); the other variants run at eight.
+// One tile, by the whole workgroup.  PRE (a pre-rendered buffer is given): the label
+// changes (BAU, when the call lists them) are first blended into the pre-rendered
+// buffer (each pixel's sign-weighted deltas are added to its stored accumulators, in
+// passes over half of a thread's pixels at tile 32), then every pixel reads the
+// inactive set's terms from it and blends the active entries on top (BAN), and the
+// image and the pixel state are written.  Without PRE the active entries are the whole
+// set.
 template <int S, int BATCH, bool PRE, bool BAU>
-__global__ __launch_bounds__(S * S < 256 ? S * S : 256)
-__attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(FwdArgs a)
+__device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int tid)
 {
     static_assert(PRE || !BAU, "label changes go into a pre-rendered buffer");
     constexpr int NT = S * S < 256 ? S * S : 256;
@@ -1078,11 +1080,11 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
     __shared__ int s_mask[BATCH];
 
     int v, tx, ty;
-    fwd_tile_of_block(a.b, v, tx, ty);
+    fwd_tile_at(a.b, ticket, v, tx, ty);
     const CamDev &cam = a.b.cams[v];
     const int tile = cam.tile_base + ty * cam.tiles_x + tx;
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int wbit = 1 << wave;
     const int col = (wave % WPR) * BW + lane % BW, row0 = (wave / WPR) * BW + lane / BW;
     const float colf = (float)col;
@@ -1265,7 +1267,7 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
     for (uint64_t base = 0; base < na; base += BATCH) {
         const int cnt = (int)(na - base < (uint64_t)BATCH ? na - base : (uint64_t)BATCH);
         __syncthreads();
-        for (int j = threadIdx.x; j < cnt; j += NT) {
+        for (int j = tid; j < cnt; j += NT) {
             const uint32_t ri = a.b.entries[off + base + j];
             s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
         }
@@ -1286,9 +1288,9 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
     // throughput counters: contributing active pairs and evaluated (in-image) pairs
     {
         __shared__ unsigned long long s_cnt[NT / 64 > 0 ? NT / 64 : 1];
-        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = npair;
+        if ((tid & 63) == 0) s_cnt[tid >> 6] = npair;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             unsigned long long t = 0;
             for (int w = 0; w < (NT + 63) / 64; ++w) t += s_cnt[w];
             const int inside = min(S, cam.W - tx * S) * min(S, cam.H - ty * S);
@@ -1320,6 +1322,37 @@ __attribute__((amdgpu_waves_per_eu(BAU && S == 32 ? 7 : 1))) void k_raster_fwd(F
     }
 }
 
+// Persistent over (view, tile): as many workgroups as the device holds at once, each
+// taking the next position of the heavy-first tile order from one device ticket until
+// the order is exhausted (every workgroup reaches the end; k_tile_order reset the
+// ticket).  The tiles of 10^2 to 10^4 entries are thus dealt longest first to whichever
+// workgroup frees up, on any XCD.  At tile 32 the variant with BAU runs at seven waves
+// per SIMD (72 registers; 24 bytes per lane go to scratch once per tile, outside the
+// blending loops; held to eight waves it spills inside them) and the others at eight.
+template <int S, int BATCH, bool PRE, bool BAU>
+__global__ __launch_bounds__(S * S < 256 ? S * S : 256)
+__attribute__((amdgpu_waves_per_eu(S == 32 ? (BAU ? 7 : 8) : 1))) void k_raster_fwd(FwdArgs a)
+{
+    __shared__ uint32_t s_ticket;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd(&a.b.counters[CNT_FQUEUE], 1u);
+        __syncthreads();
+        const uint32_t ticket = s_ticket;
+        if (ticket >= (uint32_t)a.b.T) break;
+        // Nothing derived from the thread index or the arguments is kept across tiles
+        // (it would hold registers through the blending loops): both are taken afresh
+        // for every tile, the arguments by scalar loads from their segment.
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        typedef const __attribute__((address_space(4))) char *KernArg;
+        KernArg ka = (KernArg)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ka));
+        fwd_tile<S, BATCH, PRE, BAU>(*(const FwdArgs *)ka, ticket, tid);
+        // every thread has read the ticket and is done with the LDS staging
+        __syncthreads();
+    }
+}
+
 template <typename K>
 static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const KTimer *t, const FwdArgs &a)
 {
@@ -1329,16 +1362,35 @@ static void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const K
         hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
 }
 
+// Workgroups of a persistent launch: as many as the current device runs at once (its
+// CUs times the kernel's resident workgroups per CU), at most one per work item.
+template <typename K>
+static unsigned persistent_grid(K kernel, int threads, unsigned items)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 || per_cu <= 0)
+        return items;   // one workgroup per item is always enough
+    const unsigned n = (unsigned)cus * (unsigned)per_cu;
+    return n < items ? n : items;
+}
+
+template <int S, int BATCH, bool PRE, bool BAU>
+static void raster_fwd_launch(const FwdArgs &a, hipStream_t s, const KTimer *t)
+{
+    constexpr int NT = S * S < 256 ? S * S : 256;
+    const auto kernel = k_raster_fwd<S, BATCH, PRE, BAU>;
+    launch_timed(kernel, dim3(persistent_grid(kernel, NT, (unsigned)a.b.T)), dim3(NT), s, t, a);
+}
+
 template <int S, bool PRE, bool BAU>
 static bool raster_fwd_s(const FwdArgs &a, int batch, hipStream_t s, const KTimer *t)
 {
-    constexpr int NT = S * S < 256 ? S * S : 256;
-    const dim3 grid((unsigned)a.b.T), block(NT);
     switch (batch) {
-    case 32: launch_timed(k_raster_fwd<S, 32, PRE, BAU>, grid, block, s, t, a); return true;
-    case 64: launch_timed(k_raster_fwd<S, 64, PRE, BAU>, grid, block, s, t, a); return true;
-    case 128: launch_timed(k_raster_fwd<S, 128, PRE, BAU>, grid, block, s, t, a); return true;
-    case 256: launch_timed(k_raster_fwd<S, 256, PRE, BAU>, grid, block, s, t, a); return true;
+    case 32: raster_fwd_launch<S, 32, PRE, BAU>(a, s, t); return true;
+    case 64: raster_fwd_launch<S, 64, PRE, BAU>(a, s, t); return true;
+    case 128: raster_fwd_launch<S, 128, PRE, BAU>(a, s, t); return true;
+    case 256: raster_fwd_launch<S, 256, PRE, BAU>(a, s, t); return true;
     default: return false;
     }
 }
