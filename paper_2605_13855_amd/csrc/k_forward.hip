@@ -2,6 +2,8 @@
 // blend-and-normalise / blend-and-update pass (App. A, Alg. "rasterize").
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "oit_internal.h"
 
 namespace oit {
@@ -949,11 +951,17 @@ __device__ const Rec kNoRec = {{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0
 
 // Stage record r for a tile whose first pixel centre is (x0, y0): the mean is
 // replaced by the offsets x0 - mx, y0 - my of the exponent form.  Returns the mask of
-// the tile's pixel blocks (BW x BW, WPR per row, NW in all) that the footprint box of
-// the record's (slightly widened) alpha >= 1/255 level set reaches.
-template <int BW, int WPR, int NW>
+// the row strips that the footprint box of the record's (slightly widened) alpha >=
+// 1/255 level set reaches: bit w * PPT + p for strip p of the tile's pixel block w (BW x
+// BW blocks, WPR per row, NW in all; strip p holds rows [p RSTEP, (p + 1) RSTEP) of the
+// block, the rows of a thread's pixel p), and bit kCapBit if the record's opacity may
+// reach the cap.
+constexpr int kCapBit = 30;
+
+template <int BW, int WPR, int NW, int PPT>
 __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, float y0)
 {
+    constexpr int RSTEP = BW / PPT;
     const float dx0 = x0 - r.a.x, dy0 = y0 - r.a.y;
     dst[0] = make_float4(dx0, dy0, r.a.z, r.a.w);
     dst[1] = r.b;
@@ -963,11 +971,16 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
     const float tau = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
     if (!(tau > 0.f && det > 0.f)) return 0;
     const float hx = sqrtf(tau * C / det) + 0.01f, hy = sqrtf(tau * A / det) + 0.01f;
-    int mask = 0;
+    int mask = r.b.y > kLog2NoCap ? 1 << kCapBit : 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const float bx = dx0 + (float)((w % WPR) * BW), by = dy0 + (float)((w / WPR) * BW);
-        if (bx <= hx && bx + (float)(BW - 1) >= -hx && by <= hy && by + (float)(BW - 1) >= -hy) mask |= 1 << w;
+        if (!(bx <= hx && bx + (float)(BW - 1) >= -hx)) continue;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const float sy = by + (float)(p * RSTEP);
+            if (sy <= hy && sy + (float)(RSTEP - 1) >= -hy) mask |= 1 << (w * PPT + p);
+        }
     }
     return mask;
 }
@@ -1031,20 +1044,25 @@ __device__ __forceinline__ void fold_log_t(float (&dL)[PPT], float (&Tp)[PPT], f
 
 // Blend one active record into a thread's PPT pixels (BAN accumulators, and Qs =
 // dQ/dsigma, which the backward pass uses to take dL/dsigma in a form that the float
-// rounding of F does not disturb).
-template <int PPT>
+// rounding of F does not disturb).  Only the pixels p whose bit is set in the
+// wave-uniform strip mask sp are evaluated (the record's footprint box misses the
+// others).  CAP: the record's opacity may reach the cap; otherwise alpha stays below it
+// (e <= lo < log2 of the cap) and is not clamped.
+template <int PPT, bool CAP>
 __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb, const float4 &rc, float cb,
                                              float cc, const float (&rowf)[PPT], const uint64_t (&inmask)[PPT],
-                                             unsigned long long &npair, float (&P)[PPT][3], float (&Q)[PPT],
-                                             float (&Qs)[PPT], float (&T)[PPT])
+                                             uint32_t sp, unsigned long long &npair, float (&P)[PPT][3],
+                                             float (&Q)[PPT], float (&Qs)[PPT], float (&T)[PPT])
 {
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
+        if (!((sp >> p) & 1u)) continue;
         const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
         const bool hit = e >= kLog2AlphaMin;
         npair += (unsigned long long)__builtin_popcountll(__ballot(hit) & inmask[p]);
         if (hit) {
-            const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+            const float ex = __builtin_amdgcn_exp2f(e);
+            const float al = CAP ? fminf(ex, kAlphaMax) : ex;
             const float aw = al * rc.y;
             P[p][0] = fmaf(rb.z, aw, P[p][0]);
             P[p][1] = fmaf(rb.w, aw, P[p][1]);
@@ -1085,7 +1103,6 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
     const int tile = cam.tile_base + ty * cam.tiles_x + tx;
     const float x0 = (float)(tx * S) + 0.5f, y0 = (float)(ty * S) + 0.5f;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int wbit = 1 << wave;
     const int col = (wave % WPR) * BW + lane % BW, row0 = (wave / WPR) * BW + lane / BW;
     const float colf = (float)col;
     const bool col_in = tx * S + col < cam.W;
@@ -1269,19 +1286,29 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
         __syncthreads();
         for (int j = tid; j < cnt; j += NT) {
             const uint32_t ri = a.b.entries[off + base + j];
-            s_mask[j] = stage_rec<BW, WPR, NW>(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
+            s_mask[j] = stage_rec<BW, WPR, NW, PPT>(&s_rec[3 * j], ri < a.b.Acap ? recv[ri] : kNoRec, x0, y0);
         }
         __syncthreads();
         for (int sb = 0; sb < cnt; sb += 64) {
-          uint64_t todo = __ballot(sb + lane < cnt && (s_mask[sb + lane] & wbit));
-          while (todo) {
-            const int j = sb + (int)__builtin_ctzll(todo);
-            todo &= todo - 1;
-            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
-            const float dx = ra.x + colf;
-            const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
-            blend_active<PPT>(ra, rb, rc, cb, cc, rowf, inmask, npair, P, Q, Qs, T);
-          }
+          // lane k holds record sb + k's strips of this wave; todo: records reaching any
+          const int m = sb + lane < cnt ? (s_mask[sb + lane] >> (wave * PPT)) & ((1 << PPT) - 1) : 0;
+          uint64_t todo = __ballot(m != 0);
+          auto visit = [&](auto cap) {
+            while (todo) {
+              const int k = (int)__builtin_ctzll(todo);
+              todo &= todo - 1;
+              const uint32_t sp = (uint32_t)__builtin_amdgcn_readlane(m, k);
+              const int j = sb + k;
+              const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+              const float dx = ra.x + colf;
+              const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
+              blend_active<PPT, decltype(cap)::value>(ra, rb, rc, cb, cc, rowf, inmask, sp, npair, P, Q, Qs, T);
+            }
+          };
+          if (__ballot(sb + lane < cnt && ((s_mask[sb + lane] >> kCapBit) & 1)))
+            visit(std::true_type{});
+          else
+            visit(std::false_type{});
         }
     }
 
