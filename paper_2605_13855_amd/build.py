@@ -21,7 +21,7 @@ ARCH = os.environ.get("OIT_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    "-munsafe-fp-atomics", "-Wall", "-Wshadow", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

@@ -265,13 +265,17 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float2 *pBs, 
     float dy[kGroup];
 #pragma unroll
     for (int r = 0; r < kGroup; ++r) dy[r] = dy0 + (float)(gyp + r);
+    // the column's moments over dy = yb + r are taken from sums over the row index r
+    // (c0 = sum dL/de, c1 = sum r dL/de, c2 = sum r^2 dL/de: r and r^2 are constants of
+    // the unrolled rows) and shifted by yb once per column
+    const float yb = dy0 + (float)gyp;
     // columns stay a loop: unrolled, the per-column moment updates are deferred and
     // every column's partial sums stay live
 #pragma unroll 1
     for (int c = 0; c < kGroup; ++c) {
         const float dx = dx0 + (float)(gxp + c);
         const float kb = exp_col_b(qb, dx), kc = exp_col_c(qa, lo, dx);
-        float c0 = 0.f, cy = 0.f, cyy = 0.f;
+        float c0 = 0.f, c1 = 0.f, c2 = 0.f;
 #pragma unroll
         for (int r = 0; r < kGroup; ++r) {
             const float e = exp_pix(qc, dy[r], kb, kc);
@@ -292,11 +296,15 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float2 *pBs, 
                 const float dLda = fmaf(w, diff, Bl.x * __builtin_amdgcn_rcpf(1.f - al));
                 const float dLde = (CAP ? (al < kAlphaMax ? al : 0.f) : al) * dLda;
                 c0 += dLde;
-                const float ey = dLde * dy[r];
-                cy += ey;
-                cyy = fmaf(ey, dy[r], cyy);
+                if (r > 0) {
+                    c1 = fmaf(dLde, (float)r, c1);
+                    c2 = fmaf(dLde, (float)(r * r), c2);
+                }
             }
         }
+        // sum dL/de dy = yb c0 + c1, sum dL/de dy^2 = yb^2 c0 + 2 yb c1 + c2
+        const float cy = fmaf(yb, c0, c1);
+        const float cyy = fmaf(yb, cy + c1, c2);
         o.m0 += c0;
         o.m_x = fmaf(dx, c0, o.m_x);
         o.m_xx = fmaf(dx * dx, c0, o.m_xx);
