@@ -2,7 +2,6 @@
 // blend-and-normalise / blend-and-update pass (App. A, Alg. "rasterize").
 #include <hip/hip_ext.h>
 
-#include <type_traits>
 
 #include "oit_internal.h"
 
@@ -231,6 +230,8 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
                         if (tile_hit(r, tau, cam, S, tx, ty)) ++hits;
             }
         }
+        // the raster forward clamps alpha at the cap only if some listed record can reach it
+        if (hits && lo > kLog2NoCap) atomicOr(&a.b.counters[CNT_CAP], 1u);
     } else {
         r.a = make_float4(0.f, 0.f, 0.f, 0.f);
         r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
@@ -954,10 +955,7 @@ __device__ const Rec kNoRec = {{0.f, 0.f, 0.f, 0.f}, {0.f, -1e30f, 0.f, 0.f}, {0
 // the row strips that the footprint box of the record's (slightly widened) alpha >=
 // 1/255 level set reaches: bit w * PPT + p for strip p of the tile's pixel block w (BW x
 // BW blocks, WPR per row, NW in all; strip p holds rows [p RSTEP, (p + 1) RSTEP) of the
-// block, the rows of a thread's pixel p), and bit kCapBit if the record's opacity may
-// reach the cap.
-constexpr int kCapBit = 30;
-
+// block, the rows of a thread's pixel p).
 template <int BW, int WPR, int NW, int PPT>
 __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, float y0)
 {
@@ -971,7 +969,7 @@ __device__ __forceinline__ int stage_rec(float4 *dst, const Rec &r, float x0, fl
     const float tau = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
     if (!(tau > 0.f && det > 0.f)) return 0;
     const float hx = sqrtf(tau * C / det) + 0.01f, hy = sqrtf(tau * A / det) + 0.01f;
-    int mask = r.b.y > kLog2NoCap ? 1 << kCapBit : 0;
+    int mask = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const float bx = dx0 + (float)((w % WPR) * BW), by = dy0 + (float)((w / WPR) * BW);
@@ -1001,8 +999,9 @@ __device__ __forceinline__ bool staged_hits_rect(const float4 &s0, const float4 
 
 // Blend-and-update one label-change record (staged at r) into a thread's PPT pixels:
 // sign-weighted, sigma-free sums (sign * alpha * v and the same times d, by colour),
-// and the factors (1 - alpha) into the product T of the record's sign.
-template <int PPT>
+// and the factors (1 - alpha) into the product T of the record's sign.  CAP: some
+// record of the call may reach the opacity cap (else alpha is not clamped).
+template <int PPT, bool CAP>
 __device__ __forceinline__ void bau_record(const float4 *r, float colf, const float (&rowf)[PPT], float sign,
                                            float (&dP0)[PPT][3], float (&dP1)[PPT][3], float (&dQ0)[PPT],
                                            float (&dQ1)[PPT], float (&T)[PPT])
@@ -1015,7 +1014,8 @@ __device__ __forceinline__ void bau_record(const float4 *r, float colf, const fl
     for (int p = 0; p < PPT; ++p) {
         const float e = exp_pix(rb.x, ra.y + rowf[p], cb, cc);
         if (e >= kLog2AlphaMin) {
-            const float al = fminf(__builtin_amdgcn_exp2f(e), kAlphaMax);
+            const float ex = __builtin_amdgcn_exp2f(e);
+            const float al = CAP ? fminf(ex, kAlphaMax) : ex;
             const float sav = al * sv;        // sign * alpha * v
             const float savd = sav * rc.z;    // ... * d
             dP0[p][0] = fmaf(rb.z, sav, dP0[p][0]);
@@ -1046,8 +1046,8 @@ __device__ __forceinline__ void fold_log_t(float (&dL)[PPT], float (&Tp)[PPT], f
 // dQ/dsigma, which the backward pass uses to take dL/dsigma in a form that the float
 // rounding of F does not disturb).  Only the pixels p whose bit is set in the
 // wave-uniform strip mask sp are evaluated (the record's footprint box misses the
-// others).  CAP: the record's opacity may reach the cap; otherwise alpha stays below it
-// (e <= lo < log2 of the cap) and is not clamped.
+// others).  CAP: some record of the call may reach the opacity cap; otherwise every
+// alpha stays below it (e <= lo < log2 of the cap) and is not clamped.
 template <int PPT, bool CAP>
 __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb, const float4 &rc, float cb,
                                              float cc, const float (&rowf)[PPT], const uint64_t (&inmask)[PPT],
@@ -1081,8 +1081,22 @@ __device__ __forceinline__ void blend_active(const float4 &ra, const float4 &rb,
 // inactive set's terms from it and blends the active entries on top (BAN), and the
 // image and the pixel state are written.  Without PRE the active entries are the whole
 // set.
-template <int S, int BATCH, bool PRE, bool BAU>
-__device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int tid)
+// The forward's LDS: staged records (the active entries BATCH per block, the label
+// changes 64 per wave), their strip masks, the waves' pair counts and the ticket.  One
+// instance per workgroup, whichever variant of the tile loop runs.
+template <int S, int BATCH, bool BAU>
+struct FwdShared {
+    static constexpr int NT = S * S < 256 ? S * S : 256;
+    static constexpr int NW = NT / 64;
+    static constexpr int kStage = BAU && NW * 64 > BATCH ? NW * 64 : BATCH;
+    float4 rec[kStage * 3];
+    int mask[BATCH];
+    unsigned long long cnt[NW > 0 ? NW : 1];
+    uint32_t ticket;
+};
+
+template <int S, int BATCH, bool PRE, bool BAU, bool CAP>
+__device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int tid, FwdShared<S, BATCH, BAU> &sh)
 {
     static_assert(PRE || !BAU, "label changes go into a pre-rendered buffer");
     constexpr int NT = S * S < 256 ? S * S : 256;
@@ -1092,10 +1106,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
     constexpr int NW = NT / 64;            // waves (= blocks)
     constexpr int RSTEP = 64 / BW;         // rows between one thread's pixels
     static_assert(NW == WPR * WPR && PPT * RSTEP == BW, "wave blocks must tile the tile");
-    // the active entries are staged BATCH records per block, the label changes 64 per wave
-    constexpr int kStage = BAU && NW * 64 > BATCH ? NW * 64 : BATCH;
-    __shared__ float4 s_rec[kStage * 3];
-    __shared__ int s_mask[BATCH];
+    float4 *const s_rec = sh.rec;
+    int *const s_mask = sh.mask;
 
     int v, tx, ty;
     fwd_tile_at(a.b, ticket, v, tx, ty);
@@ -1232,7 +1244,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
                 while (todo_p) {
                     const int j = (int)__builtin_ctzll(todo_p);
                     todo_p &= todo_p - 1;
-                    bau_record<PB>(wrec + 3 * j, colf, rows, 1.f, dP0, dP1, dQ0, dQ1, Tp);
+                    bau_record<PB, CAP>(wrec + 3 * j, colf, rows, 1.f, dP0, dP1, dQ0, dQ1, Tp);
                     if (++since_fold == kFold) {
                         since_fold = 0;
                         fold_log_t<PB>(dL, Tp, Tm);
@@ -1241,7 +1253,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
                 while (todo_m) {
                     const int j = (int)__builtin_ctzll(todo_m);
                     todo_m &= todo_m - 1;
-                    bau_record<PB>(wrec + 3 * j, colf, rows, -1.f, dP0, dP1, dQ0, dQ1, Tm);
+                    bau_record<PB, CAP>(wrec + 3 * j, colf, rows, -1.f, dP0, dP1, dQ0, dQ1, Tm);
                     if (++since_fold == kFold) {
                         since_fold = 0;
                         fold_log_t<PB>(dL, Tp, Tm);
@@ -1293,28 +1305,22 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
           // lane k holds record sb + k's strips of this wave; todo: records reaching any
           const int m = sb + lane < cnt ? (s_mask[sb + lane] >> (wave * PPT)) & ((1 << PPT) - 1) : 0;
           uint64_t todo = __ballot(m != 0);
-          auto visit = [&](auto cap) {
-            while (todo) {
-              const int k = (int)__builtin_ctzll(todo);
-              todo &= todo - 1;
-              const uint32_t sp = (uint32_t)__builtin_amdgcn_readlane(m, k);
-              const int j = sb + k;
-              const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
-              const float dx = ra.x + colf;
-              const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
-              blend_active<PPT, decltype(cap)::value>(ra, rb, rc, cb, cc, rowf, inmask, sp, npair, P, Q, Qs, T);
-            }
-          };
-          if (__ballot(sb + lane < cnt && ((s_mask[sb + lane] >> kCapBit) & 1)))
-            visit(std::true_type{});
-          else
-            visit(std::false_type{});
+          while (todo) {
+            const int k = (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t sp = (uint32_t)__builtin_amdgcn_readlane(m, k);
+            const int j = sb + k;
+            const float4 ra = s_rec[3 * j], rb = s_rec[3 * j + 1], rc = s_rec[3 * j + 2];
+            const float dx = ra.x + colf;
+            const float cb = exp_col_b(ra.w, dx), cc = exp_col_c(ra.z, rb.y, dx);
+            blend_active<PPT, CAP>(ra, rb, rc, cb, cc, rowf, inmask, sp, npair, P, Q, Qs, T);
+          }
         }
     }
 
     // throughput counters: contributing active pairs and evaluated (in-image) pairs
     {
-        __shared__ unsigned long long s_cnt[NT / 64 > 0 ? NT / 64 : 1];
+        unsigned long long *const s_cnt = sh.cnt;
         if ((tid & 63) == 0) s_cnt[tid >> 6] = npair;
         __syncthreads();
         if (tid == 0) {
@@ -1349,6 +1355,29 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs &a, uint32_t ticket, int 
     }
 }
 
+// The persistent loop: tiles from the ticket until the heavy-first order is exhausted.
+template <int S, int BATCH, bool PRE, bool BAU, bool CAP>
+__device__ __forceinline__ void fwd_tiles(const FwdArgs &a, FwdShared<S, BATCH, BAU> &sh)
+{
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = atomicAdd(&a.b.counters[CNT_FQUEUE], 1u);
+        __syncthreads();
+        const uint32_t ticket = sh.ticket;
+        if (ticket >= (uint32_t)a.b.T) break;
+        // Nothing derived from the thread index or the arguments is kept across tiles
+        // (it would hold registers through the blending loops): both are taken afresh
+        // for every tile, the arguments by scalar loads from their segment.
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        typedef const __attribute__((address_space(4))) char *KernArg;
+        KernArg ka = (KernArg)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ka));
+        fwd_tile<S, BATCH, PRE, BAU, CAP>(*(const FwdArgs *)ka, ticket, tid, sh);
+        // every thread has read the ticket and is done with the LDS staging
+        __syncthreads();
+    }
+}
+
 // Persistent over (view, tile): as many workgroups as the device holds at once, each
 // taking the next position of the heavy-first tile order from one device ticket until
 // the order is exhausted (every workgroup reaches the end; k_tile_order reset the
@@ -1360,24 +1389,12 @@ template <int S, int BATCH, bool PRE, bool BAU>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256)
 __attribute__((amdgpu_waves_per_eu(S == 32 ? (BAU ? 7 : 8) : 1))) void k_raster_fwd(FwdArgs a)
 {
-    __shared__ uint32_t s_ticket;
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(&a.b.counters[CNT_FQUEUE], 1u);
-        __syncthreads();
-        const uint32_t ticket = s_ticket;
-        if (ticket >= (uint32_t)a.b.T) break;
-        // Nothing derived from the thread index or the arguments is kept across tiles
-        // (it would hold registers through the blending loops): both are taken afresh
-        // for every tile, the arguments by scalar loads from their segment.
-        int tid = (int)threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        typedef const __attribute__((address_space(4))) char *KernArg;
-        KernArg ka = (KernArg)__builtin_amdgcn_kernarg_segment_ptr();
-        asm volatile("" : "+s"(ka));
-        fwd_tile<S, BATCH, PRE, BAU>(*(const FwdArgs *)ka, ticket, tid);
-        // every thread has read the ticket and is done with the LDS staging
-        __syncthreads();
-    }
+    __shared__ FwdShared<S, BATCH, BAU> sh;
+    // the opacity clamp is compiled in only if a record of the call can reach the cap
+    if (a.b.counters[CNT_CAP])
+        fwd_tiles<S, BATCH, PRE, BAU, true>(a, sh);
+    else
+        fwd_tiles<S, BATCH, PRE, BAU, false>(a, sh);
 }
 
 template <typename K>

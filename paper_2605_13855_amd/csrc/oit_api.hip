@@ -422,7 +422,7 @@ oit_status oit_render_fwd(const oit_splats *splats, const float *sigma, const fl
     const Buffers b = buffers(p, ws, n_views, tuning);
     const RowList rl = rows(cap, active_idx, n_active, delta_idx, delta_sign, n_delta, p);
     upload_cams(p.cams_host, n_views, b.cams, s);
-    fill_u32(b.counters + CNT_PAIRS, 4, 0u, s);
+    fill_u32(b.counters + CNT_PAIRS, CNT_CAP + 1 - CNT_PAIRS, 0u, s);   // pair and cap counters
     auto mark = [&](int k) {
         if (g_timing_on) (void)hipEventRecord(g_ev[k], s);
     };

@@ -27,11 +27,12 @@ constexpr int kSigPreParts = 4096;             // blocks of the preprocess backw
 // (CNT_PAIRS and CNT_EVAL are 64-bit counters occupying two slots each)
 // CNT_NPAIRS: (listed record, view) pairs of the call; CNT_SORT_N: tile entries that fit
 // the pair capacity (the sorted list's length)
+// CNT_CAP: nonzero if a record listed by the forward call may reach the opacity cap
 // CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue tickets
 // CNT_BOX_ITEMS: backward work items that took the footprint-box walk
 // CNT_FQUEUE: the forward's work-queue ticket (positions in the heavy-first tile order)
-enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_XQUEUE = 8,
-       CNT_BOX_ITEMS = 16, CNT_FQUEUE = 17, CNT_SLOTS = 32 };
+enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_CAP = 8,
+       CNT_XQUEUE = 9, CNT_BOX_ITEMS = 17, CNT_FQUEUE = 18, CNT_SLOTS = 32 };
 constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
 struct SplatPtrs {

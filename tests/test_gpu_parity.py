@@ -436,7 +436,25 @@ def test_active_set_render_equals_dense(tile, batch):
     Tile 32 runs the forward variant with label changes at six waves per SIMD, the
     launch of the timed step, at every LDS batch."""
     log(f"active set vs dense, 2 views, tile {tile}, batch {batch}")
-    sc = scenes.random_scene(31, 4000, 96, 80, n_views=2, mean_range=1.0)
+    active_set_case(scenes.random_scene(31, 4000, 96, 80, n_views=2, mean_range=1.0), tile, batch)
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_opacity_cap_parity(tile):
+    """Splats whose opacity exceeds the 0.99 cap (Sec. 3, alpha = min(0.99, ...)): the
+    forward takes its clamping variant only when a listed record can reach the cap, so a
+    scene with a tenth of its splats at opacity 0.9975 is compared with the oracle dense
+    and through the active-set path, the capped splats among the active rows and the
+    label changes of both signs."""
+    sc = scenes.random_scene(37, 3000, 96, 80, n_views=2, mean_range=1.0)
+    sc.params["opacity_logit"][0, ::10] = 6.0
+    log(f"opacity cap, dense, tile {tile}")
+    dense_case(sc, tile, 64)
+    log(f"opacity cap, active set, tile {tile}")
+    active_set_case(sc, tile, 64)
+
+
+def active_set_case(sc, tile, batch):
     n = sc.n
     params = params_to_device(sc.params)
     sigma = torch.tensor([sc.sigma], device=DEV)
