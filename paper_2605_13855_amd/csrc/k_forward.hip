@@ -1383,8 +1383,9 @@ __device__ __forceinline__ void fwd_tiles(const FwdArgs &a, FwdShared<S, BATCH, 
 // the order is exhausted (every workgroup reaches the end; k_tile_order reset the
 // ticket).  The tiles of 10^2 to 10^4 entries are thus dealt longest first to whichever
 // workgroup frees up, on any XCD.  At tile 32 the variant with BAU runs at seven waves
-// per SIMD (72 registers; 24 bytes per lane go to scratch once per tile, outside the
-// blending loops; held to eight waves it spills inside them) and the others at eight.
+// per SIMD (72 registers; 24-28 bytes per lane go to scratch once per tile, outside the
+// blending loops; held to eight waves it spills inside them) and the others at eight
+// (the dense one with 8 bytes per lane of scratch, also once per tile).
 template <int S, int BATCH, bool PRE, bool BAU>
 __global__ __launch_bounds__(S * S < 256 ? S * S : 256)
 __attribute__((amdgpu_waves_per_eu(S == 32 ? (BAU ? 7 : 8) : 1))) void k_raster_fwd(FwdArgs a)
