@@ -106,6 +106,11 @@ __global__ __launch_bounds__(256) void k_l1_loss(LossArgs a)
     if (threadIdx.x == 0) a.b.loss_part[blockIdx.x] = t;
 }
 
+void launch_sum_shares(const double *parts, int n, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_shares, dim3(1), dim3(kSumThreads), 0, s, parts, n, (const double *)nullptr, 0, dst);
+}
+
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s)
 {

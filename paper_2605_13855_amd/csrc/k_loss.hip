@@ -22,7 +22,8 @@ struct LossArgs2 {
     const float *image, *target;
     float *grad;
     float *maps;                   // [3 partials][3 ch][total_px]
-    double *acc;                   // [2]: sum |C - I| / (3HW), sum SSIM / (3HW)
+    double *parts;                 // [2][blocks]: each block's share of sum |C - I| / (3HW), then of
+                                   // sum SSIM / (3HW)
     int64_t total_px;
     float lambda;
     float g[11];
@@ -51,28 +52,17 @@ __device__ __forceinline__ void loss_tile(const LossArgs2 &a, int blk, int &v, i
     y0 = (lt / tx_n) * kLT;
 }
 
-__device__ __forceinline__ void block_add2(double v0, double v1, double *dst)
+// The block's sum of v (lanes by a butterfly, waves in turn), written by thread 0 to
+// *dst: each block's share is summed afterwards in a fixed order, so the loss value does
+// not depend on the order in which the blocks finish.
+__device__ __forceinline__ void block_share(double v, double *dst)
 {
-    __shared__ double s0[4], s1[4];
-    for (int o = 32; o > 0; o >>= 1) {
-        v0 += __shfl_xor(v0, o);
-        v1 += __shfl_xor(v1, o);
-    }
+    __shared__ double s0[4];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s0[w] = v0;
-        s1[w] = v1;
-    }
+    if ((threadIdx.x & 63) == 0) s0[w] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int k = 0; k < 4; ++k) {
-            t0 += s0[k];
-            t1 += s1[k];
-        }
-        if (t0 != 0.0) unsafeAtomicAdd(dst, t0);
-        if (t1 != 0.0) unsafeAtomicAdd(dst + 1, t1);
-    }
+    if (threadIdx.x == 0) *dst = s0[0] + s0[1] + s0[2] + s0[3];
 }
 
 // pass 1: window statistics, SSIM and its partials
@@ -142,7 +132,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossArgs2 a)
         a.maps[(2 * 3 + ch) * plane + pix] = dexy;
         ssum = (double)S / (3.0 * (double)HW);
     }
-    block_add2(0.0, ssum, a.acc);
+    block_share(ssum, a.parts + gridDim.x + blockIdx.x);
 }
 
 // pass 2: adjoint filtering of the partials, L1 term, dL/dC
@@ -192,7 +182,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossArgs2 a)
         a.grad[off] = (1.f - a.lambda) * dl1 + a.lambda * dssim;
         l1 = fabs((double)x - (double)y) / (3.0 * (double)HW);
     }
-    block_add2(l1, 0.0, a.acc);
+    block_share(l1, a.parts + blockIdx.x);
 }
 
 __global__ void k_loss_combine(const double *acc, int n_views, float lambda, double *loss)
@@ -203,7 +193,7 @@ __global__ void k_loss_combine(const double *acc, int n_views, float lambda, dou
 
 void launch_l1_dssim(const CamDev *cams, int n_views, int64_t total_px, int tiles16, const float *image,
                      const float *target, float lambda, float *grad, double *loss, float *maps, double *acc,
-                     hipStream_t s)
+                     double *parts, hipStream_t s)
 {
     LossArgs2 a;
     a.cams = cams;
@@ -213,7 +203,7 @@ void launch_l1_dssim(const CamDev *cams, int n_views, int64_t total_px, int tile
     a.target = target;
     a.grad = grad;
     a.maps = maps;
-    a.acc = acc;
+    a.parts = parts;
     a.total_px = total_px;
     a.lambda = lambda;
     double g[11], sum = 0.0;
@@ -223,10 +213,11 @@ void launch_l1_dssim(const CamDev *cams, int n_views, int64_t total_px, int tile
         sum += g[k];
     }
     for (int k = 0; k < 11; ++k) a.g[k] = (float)(g[k] / sum);
-    fill_f64(acc, 2, 0.0, s);
     const unsigned blocks = (unsigned)(3 * tiles16);
     hipLaunchKernelGGL(k_ssim_stats, dim3(blocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_ssim_grad, dim3(blocks), dim3(256), 0, s, a);
+    launch_sum_shares(parts, (int)blocks, acc, s);
+    launch_sum_shares(parts + blocks, (int)blocks, acc + 1, s);
     hipLaunchKernelGGL(k_loss_combine, dim3(1), dim3(1), 0, s, acc, n_views, lambda, loss);
 }
 

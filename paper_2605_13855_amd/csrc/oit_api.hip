@@ -459,7 +459,7 @@ oit_status oit_l1_loss(const float *image, const float *target, const oit_camera
 
 namespace {
 struct LossPlan {
-    size_t cams, acc, maps, total;
+    size_t cams, acc, parts, maps, total;
     int64_t total_px;
     int tiles16;
 };
@@ -477,6 +477,8 @@ oit_status loss_plan(const oit_camera *cams, int32_t n_views, LossPlan &lp, Plan
     o = align256(o + sizeof(CamDev) * kMaxViews);
     lp.acc = o;
     o = align256(o + 2 * sizeof(double));
+    lp.parts = o;   // per-block shares of both sums, one block per 16 x 16 tile and channel
+    o = align256(o + 2 * 3 * sizeof(double) * (size_t)p.T);
     lp.maps = o;
     o = align256(o + 9 * sizeof(float) * (size_t)p.total_px);
     lp.total = o;
@@ -509,7 +511,7 @@ oit_status oit_l1_dssim_loss(const float *image, const float *target, const oit_
     CamDev *dcams = (CamDev *)(w + lp.cams);
     upload_cams(p.cams_host, n_views, dcams, s);
     launch_l1_dssim(dcams, n_views, lp.total_px, lp.tiles16, image, target, lambda, grad_image, loss,
-                    (float *)(w + lp.maps), (double *)(w + lp.acc), s);
+                    (float *)(w + lp.maps), (double *)(w + lp.acc), (double *)(w + lp.parts), s);
     return check_launch("oit_l1_dssim_loss");
 }
 

@@ -122,6 +122,8 @@ bool launch_raster_fwd(const Buffers &b, const float *sigma, const float bg[3], 
 
 void launch_l1_loss(const Buffers &b, const float *image, const float *target, float *grad, double *loss,
                     hipStream_t s);
+// *dst = sum of parts[0 .. n), added in a fixed order by one block
+void launch_sum_shares(const double *parts, int n, double *dst, hipStream_t s);
 void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], const float *pre,
                      const float *grad_image, const float *pixstate, double *grad_sigma, hipStream_t s);
 bool launch_raster_bwd(const Buffers &b, const RowList &rl, hipStream_t s, const KTimer *t = nullptr);
@@ -129,9 +131,10 @@ void launch_preprocess_bwd(const SplatPtrs &sp, const float *sigma, const RowLis
                            const GradPtrs &g, double *grad_sigma, float *score, const float eps[6],
                            hipStream_t s);
 
+// acc: the two sums (L1, SSIM); parts: 2 x 3 x tiles16 per-block shares of them
 void launch_l1_dssim(const CamDev *cams, int n_views, int64_t total_px, int tiles16, const float *image,
                      const float *target, float lambda, float *grad, double *loss, float *maps, double *acc,
-                     hipStream_t s);
+                     double *parts, hipStream_t s);
 
 struct SelectBuffers {
     int32_t *status;

@@ -45,3 +45,11 @@ def test_l1_dssim_matches_oracle(sizes, lam):
           flush=True)
     assert float(loss.item()) == pytest.approx(L_ref, rel=1e-5)
     assert rel <= 1e-4
+    # the loss value adds the blocks' shares in a fixed order: a second call on a freshly
+    # filled workspace gives the same bits
+    ws.fill_(255)
+    loss2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    grad2 = torch.zeros_like(image)
+    oit.l1_dssim_loss(image, target, arr, len(cams), lam, grad2, loss2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(loss, loss2) and torch.equal(grad, grad2)
