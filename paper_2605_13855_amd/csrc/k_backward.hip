@@ -213,16 +213,17 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 
 // ---------------------------------------------------------------------------------
 // raster backward (the paper's per-splat backward, Sec. 4.2): one wave per work item
-// = (tile, 64 active entries), one splat per lane.  The tile is walked in 8 x 8 pixel
-// groups and a group that no lane's footprint box reaches is skipped.  For each
-// remaining group the wave stages the 64 pixels' constants in its LDS slice (one
-// pixel per lane; the next group's are fetched from memory while the current one is
-// processed), then every lane walks the 64 pixels column by column and reads each
-// pixel's constants as a uniform LDS broadcast.  Per splat, the colour and weight
-// sums and the moments of dL/de over the pixel offsets stay in registers; they give
-// the 10 screen-space partials once per work item, stored with plain stores in the
-// entry's own row at its unsorted slot (no atomics: a (record, view) pair's slots are
-// contiguous, and the preprocess backward sums them in a fixed order).
+// = (tile, 64 active entries), one splat per lane.  The tile is cut into 8 x 8 pixel
+// groups and a group that no lane's footprint box reaches is skipped.  The reached
+// groups are taken four at a time: the wave stages their pixels' constants in its LDS
+// slice, lists the (splat, group) pairs of the four (a splat and a group its box
+// reaches) and deals them 64 per round to its lanes, so that a lane walks a group only
+// for a splat that reaches it (items whose boxes are all small walk each lane's own box
+// instead).  Per splat, the colour and weight sums and the moments of dL/de over the
+// pixel offsets end in the splat's own lane; they give the 10 screen-space partials
+// once per work item, stored with plain stores in the entry's own row at its unsorted
+// slot (no atomics: a (record, view) pair's slots are contiguous, and the preprocess
+// backward sums them in a fixed order).
 //
 // Work items go to the XCDs in blocks of consecutive items (block b to XCD b mod 8), so
 // that each XCD gets a mix of the batch and the waves working on one tile share an L2;
@@ -325,6 +326,12 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float2 *pBs, 
 // 64 slots.
 constexpr int kBoxPerGroup = 21;
 
+// Groups of a pair window: their pixel constants are staged together in a wave's slice,
+// kSlot entries apart (one more than a group's 64 pixels), so that lanes reading the
+// same pixel of different groups hit different LDS banks.
+constexpr int kWin = 4;
+constexpr int kSlot = 65;
+
 // The entry's 10 screen-space partials from the lane's sums:
 // de/dlo = 1, de/dqa = dx^2, de/dqb = dx dy, de/dqc = dy^2,
 // de/dmx = -(2 qa dx + qb dy), de/dmy = -(qb dx + 2 qc dy); the ln 2 of d alpha / de.
@@ -339,7 +346,8 @@ __device__ __forceinline__ void write_partials(float *dst, float qa, float qb, f
 template <int S>
 // boxed: the wave's count of items walked box by box (for the counters)
 __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
-                                         float4 (*s_c)[64], float2 (*s_B)[64], uint32_t &boxed)
+                                         float4 (*s_c)[kWin * kSlot], float2 (*s_B)[kWin * kSlot],
+                                         uint8_t (*s_pair)[kWin * 64], uint32_t &boxed)
 {
     constexpr int GX = S / kGroup;   // groups per tile edge
     const uint64_t cap = (uint64_t)b.pair_cap;
@@ -382,13 +390,15 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     // this entry's row of screen-space partials, at its unsorted slot (written for every
     // valid lane)
     float *dst = b.ep + (size_t)(valid ? b.orig[off + j] : 0u) * kEpStride;
-    // bit g: some lane's footprint box reaches group g (pixel offsets [g0, g0 + 7])
-    uint32_t mask = 0;
+    // bit g of mask: some lane's footprint box reaches group g (pixel offsets [g0, g0 + 7]);
+    // bit g of my: this lane's box does
+    uint32_t mask = 0, my = 0;
 #pragma unroll
     for (int g = 0; g < GX * GX; ++g) {
         const float gx0 = dx0 + (float)((g % GX) * kGroup), gy0 = dy0 + (float)((g / GX) * kGroup);
         const bool hit = hx >= 0.f && gx0 <= hx && gx0 + (float)(kGroup - 1) >= -hx && gy0 <= hy &&
                          gy0 + (float)(kGroup - 1) >= -hy;
+        if (hit) my |= 1u << g;
         if (__ballot(hit)) mask |= 1u << g;
     }
     if (mask == 0) {
@@ -485,41 +495,124 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
     };
 
+    // (splat, group) pairs dealt to the lanes.  The reached groups are taken kWin at a
+    // time; the window's pixel constants are staged in the wave's LDS slice (slot k holds
+    // the window's k-th group, one pixel per lane).  The window's pairs -- a lane's splat
+    // and a group of the window that its box reaches -- are listed splat by splat and
+    // dealt 64 per round, one per lane; each lane walks its pair's group for the pair's
+    // splat, whose parameters it reads from the owning lane.  A splat's consecutive pairs
+    // in a round (at most kWin) are then summed at the first of them and added into the
+    // owning lane's sums.  Lanes thus walk pixels for splats that reach them, instead of
+    // every lane walking every group that some lane reaches.
     BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int g = __builtin_ctz(mask);
-    mask &= mask - 1;
-    float4 nc;
-    float2 nB;
-    fetch(g, nc, nB);
-    for (;;) {
-        s_c[wave][lane] = nc;
-        s_B[wave][lane] = nB;
-        int gn = -1;
-        if (mask) {
-            gn = __builtin_ctz(mask);
-            mask &= mask - 1;
-            fetch(gn, nc, nB);
+    float4 *const wc = s_c[wave];
+    float2 *const wB = s_B[wave];
+    uint8_t *const wp = s_pair[wave];
+    uint32_t rest = mask;
+    while (rest) {
+        uint32_t wpack = 0;   // the window's groups, 4 bits each
+        int nw = 0;
+        while (rest && nw < kWin) {
+            wpack |= (uint32_t)__builtin_ctz(rest) << (4 * nw);
+            rest &= rest - 1;
+            ++nw;
+        }
+        uint32_t slots = 0;   // window slots of this lane's pairs
+#pragma unroll
+        for (int k = 0; k < kWin; ++k) {
+            if (k < nw) {
+                const int g = (int)((wpack >> (4 * k)) & 15u);
+                float4 c;
+                float2 Bv;
+                fetch(g, c, Bv);
+                wc[k * kSlot + lane] = c;
+                wB[k * kSlot + lane] = Bv;
+                if ((my >> g) & 1u) slots |= 1u << k;
+            }
+        }
+        // the lane's first pair in the window's list (exclusive prefix over the wave)
+        const int cnt = __builtin_popcount(slots);
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const int pfx = incl - cnt;
+        const int P = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));   // pairs in the window
+        {
+            int q = pfx;
+#pragma unroll
+            for (int k = 0; k < kWin; ++k)
+                if ((slots >> k) & 1u) wp[q++] = (uint8_t)((lane << 2) | k);
         }
         __builtin_amdgcn_wave_barrier();
-        const int gxp = (g % GX) * kGroup, gyp = (g / GX) * kGroup;
-        if (may_cap)
-            bwd_group<true>(s_c[wave], s_B[wave], gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
-        else
-            bwd_group<false>(s_c[wave], s_B[wave], gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
+        for (int base = 0; base < P; base += 64) {
+            const int t = base + lane;
+            const bool on = t < P;
+            const int e = on ? (int)wp[t] : 0;
+            const int owner = e >> 2, slot = e & 3;
+            const int g = (int)((wpack >> (4 * slot)) & 15u);
+            // the pair's splat (a lane past the last pair evaluates nothing: lo = -1e30).
+            // Every lane takes part in every shuffle: a lane left out of one (a shuffle
+            // under a branch) does not supply its value to the others.
+            const float pdx0 = __shfl(dx0, owner), pdy0 = __shfl(dy0, owner);
+            const float pqa = __shfl(qa, owner), pqb = __shfl(qb, owner), pqc = __shfl(qc, owner);
+            const float slo = __shfl(lo, owner);
+            const float plo = on ? slo : -1e30f;
+            const float pcr = __shfl(cr, owner), pcg = __shfl(cg, owner), pcb = __shfl(cb, owner);
+            const float pw = __shfl(w, owner);
+            BwdSums p = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const int gxp = (g % GX) * kGroup, gyp = (g / GX) * kGroup;
+            if (may_cap)
+                bwd_group<true>(wc + slot * kSlot, wB + slot * kSlot, gxp, gyp, pdx0, pdy0, pqa, pqb, pqc, plo, pcr, pcg, pcb,
+                                pw, p);
+            else
+                bwd_group<false>(wc + slot * kSlot, wB + slot * kSlot, gxp, gyp, pdx0, pdy0, pqa, pqb, pqc, plo, pcr, pcg, pcb,
+                                 pw, p);
+            // segments of at most kWin lanes with one owner: two steps sum each at its head
+            const int own1 = __shfl_down(owner, 1), own2 = __shfl_down(owner, 2);
+            const bool s1 = lane + 1 < 64 && t + 1 < P && own1 == owner;
+            const bool s2 = lane + 2 < 64 && t + 2 < P && own2 == owner;
+            // this lane as owner: its pairs in the round start at lane `head`
+            const bool mine = cnt > 0 && pfx < base + 64 && pfx + cnt > base;
+            const int head = (pfx > base ? pfx : base) - base;
+            auto add = [&](float v, float &dst) {
+                const float a1 = __shfl_down(v, 1);
+                v += s1 ? a1 : 0.f;
+                const float a2 = __shfl_down(v, 2);
+                v += s2 ? a2 : 0.f;
+                const float h = __shfl(v, head);
+                if (mine) dst += h;
+            };
+            add(p.g_cr, o.g_cr);
+            add(p.g_cg, o.g_cg);
+            add(p.g_cb, o.g_cb);
+            add(p.g_w, o.g_w);
+            add(p.g_h, o.g_h);
+            add(p.m0, o.m0);
+            add(p.m_x, o.m_x);
+            add(p.m_y, o.m_y);
+            add(p.m_xx, o.m_xx);
+            add(p.m_xy, o.m_xy);
+            add(p.m_yy, o.m_yy);
+        }
+        // the window's slices are rewritten by the next window
         __builtin_amdgcn_wave_barrier();
-        if (gn < 0) break;
-        g = gn;
     }
     if (valid) write_partials(dst, qa, qb, qc, w, o);
 }
 
-// Six waves per SIMD: the kernel then keeps its 78 registers without spilling; held to
-// eight (64 registers) it spilled in the walks and ran 4-6% slower.
+// Five waves per SIMD: 96 registers, with 36 bytes per lane of scratch used per item and
+// per window of groups, none inside the rounds.  At config 4 (5% active) four waves
+// keep everything in registers and ran 4% slower; six waves spilled 92 bytes per lane
+// inside the walks and ran 15% slower.
 template <int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_raster_bwd(BwdArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raster_bwd(BwdArgs a)
 {
-    __shared__ float4 s_c[4][64];
-    __shared__ float2 s_B[4][64];
+    __shared__ float4 s_c[4][kWin * kSlot];
+    __shared__ float2 s_B[4][kWin * kSlot];
+    __shared__ uint8_t s_pair[4][kWin * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t total = a.b.counters[CNT_TOTAL_CHUNKS];
     if (total > a.b.max_chunks) total = a.b.max_chunks;
@@ -537,7 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
         // the ticket-th item of this XCD: block xcd + 8 (ticket / B), offset ticket % B
         const uint64_t item = (((uint64_t)xcd + (uint64_t)kXcds * (ticket >> lb)) << lb) + (ticket & ((1u << lb) - 1u));
         if (item >= total) break;   // items grow with the ticket: the queue is drained
-        bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, boxed);
+        bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, s_pair, boxed);
     }
     // one atomic per block for the box-walk counter
     __shared__ uint32_t s_boxed[4];
