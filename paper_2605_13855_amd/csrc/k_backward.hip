@@ -219,7 +219,8 @@ void launch_pixconst(const Buffers &b, const float *sigma, const float bg[3], co
 // slice, lists the (splat, group) pairs of the four (a splat and a group its box
 // reaches) and deals them 64 per round to its lanes, so that a lane walks a group only
 // for a splat that reaches it (items whose boxes are all small walk each lane's own box
-// instead).  Per splat, the colour and weight sums and the moments of dL/de over the
+// instead, and items whose splats nearly all reach all their groups are walked group by
+// group by the whole wave).  Per splat, the colour and weight sums and the moments of dL/de over the
 // pixel offsets end in the splat's own lane; they give the 10 screen-space partials
 // once per work item, stored with plain stores in the entry's own row at its unsorted
 // slot (no atomics: a (record, view) pair's slots are contiguous, and the preprocess
@@ -508,6 +509,54 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     float4 *const wc = s_c[wave];
     float2 *const wB = s_B[wave];
     uint8_t *const wp = s_pair[wave];
+
+    // Where the dealt rounds would be nearly as many as the reached groups (most splats of
+    // the item reach most of its groups), the whole wave walks every reached group with
+    // a uniform LDS broadcast of each pixel's constants instead (the next group's are
+    // fetched while the current one is walked): no shuffles, no window staging.
+    int rounds = 0;
+    {
+        uint32_t r = mask;
+        while (r) {
+            int pw = 0;
+            for (int k = 0; k < kWin && r; ++k) {
+                const int g = __builtin_ctz(r);
+                r &= r - 1;
+                pw += (int)__builtin_popcountll(__ballot((my >> g) & 1u));
+            }
+            rounds += (pw + 63) >> 6;
+        }
+    }
+    if (10 * rounds >= 9 * __builtin_popcount(mask)) {
+        uint32_t rest = mask;
+        int g = __builtin_ctz(rest);
+        rest &= rest - 1;
+        float4 nc;
+        float2 nB;
+        fetch(g, nc, nB);
+        for (;;) {
+            wc[lane] = nc;
+            wB[lane] = nB;
+            int gn = -1;
+            if (rest) {
+                gn = __builtin_ctz(rest);
+                rest &= rest - 1;
+                fetch(gn, nc, nB);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int gxp = (g % GX) * kGroup, gyp = (g / GX) * kGroup;
+            if (may_cap)
+                bwd_group<true>(wc, wB, gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
+            else
+                bwd_group<false>(wc, wB, gxp, gyp, dx0, dy0, qa, qb, qc, lo, cr, cg, cb, w, o);
+            __builtin_amdgcn_wave_barrier();
+            if (gn < 0) break;
+            g = gn;
+        }
+        if (valid) write_partials(dst, qa, qb, qc, w, o);
+        return;
+    }
+
     uint32_t rest = mask;
     while (rest) {
         uint32_t wpack = 0;   // the window's groups, 4 bits each
