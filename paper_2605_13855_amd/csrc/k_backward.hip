@@ -496,15 +496,6 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
     };
 
-    // (splat, group) pairs dealt to the lanes.  The reached groups are taken kWin at a
-    // time; the window's pixel constants are staged in the wave's LDS slice (slot k holds
-    // the window's k-th group, one pixel per lane).  The window's pairs -- a lane's splat
-    // and a group of the window that its box reaches -- are listed splat by splat and
-    // dealt 64 per round, one per lane; each lane walks its pair's group for the pair's
-    // splat, whose parameters it reads from the owning lane.  A splat's consecutive pairs
-    // in a round (at most kWin) are then summed at the first of them and added into the
-    // owning lane's sums.  Lanes thus walk pixels for splats that reach them, instead of
-    // every lane walking every group that some lane reaches.
     BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float4 *const wc = s_c[wave];
     float2 *const wB = s_B[wave];
@@ -557,6 +548,15 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         return;
     }
 
+    // (splat, group) pairs dealt to the lanes.  The reached groups are taken kWin at a
+    // time; the window's pixel constants are staged in the wave's LDS slice (slot k holds
+    // the window's k-th group, one pixel per lane).  The window's pairs -- a lane's splat
+    // and a group of the window that its box reaches -- are listed splat by splat and
+    // dealt 64 per round, one per lane; each lane walks its pair's group for the pair's
+    // splat, whose parameters it reads from the owning lane.  A splat's consecutive pairs
+    // in a round (at most kWin) are then summed at the first of them and added into the
+    // owning lane's sums.  Lanes thus walk pixels for splats that reach them, instead of
+    // every lane walking every group that some lane reaches.
     uint32_t rest = mask;
     while (rest) {
         uint32_t wpack = 0;   // the window's groups, 4 bits each
@@ -626,13 +626,13 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
             // this lane as owner: its pairs in the round start at lane `head`
             const bool mine = cnt > 0 && pfx < base + 64 && pfx + cnt > base;
             const int head = (pfx > base ? pfx : base) - base;
-            auto add = [&](float v, float &dst) {
+            auto add = [&](float v, float &sum) {
                 const float a1 = __shfl_down(v, 1);
                 v += s1 ? a1 : 0.f;
                 const float a2 = __shfl_down(v, 2);
                 v += s2 ? a2 : 0.f;
                 const float h = __shfl(v, head);
-                if (mine) dst += h;
+                if (mine) sum += h;
             };
             add(p.g_cr, o.g_cr);
             add(p.g_cg, o.g_cg);
@@ -652,10 +652,10 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
     if (valid) write_partials(dst, qa, qb, qc, w, o);
 }
 
-// Five waves per SIMD: 96 registers, with 36 bytes per lane of scratch used per item and
-// per window of groups, none inside the rounds.  At config 4 (5% active) four waves
-// keep everything in registers and ran 4% slower; six waves spilled 92 bytes per lane
-// inside the walks and ran 15% slower.
+// Five waves per SIMD: 96 registers, with 48 bytes per lane of scratch used per item, per
+// window and per group of the whole-wave walk, none inside the rounds or the columns.
+// At config 4 (5% active) four waves keep everything in registers and ran 4% slower;
+// six waves spilled 92 bytes per lane inside the walks and ran 15% slower.
 template <int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raster_bwd(BwdArgs a)
 {
