@@ -322,10 +322,12 @@ __device__ __forceinline__ void bwd_group(const float4 *pcs, const float2 *pBs, 
 }
 
 // Box mode is taken when the largest footprint box is at most kBoxPerGroup pixels per
-// reached group: a box pixel costs about three times a group pixel slot (its own
-// exponent terms, a memory read of the constants, the full moments), and a group costs
-// 64 slots.
-constexpr int kBoxPerGroup = 21;
+// reached group.  A box pixel costs several group pixel slots (its own exponent terms, a
+// memory read of the constants, the full moments); with the groups' pairs dealt to the
+// lanes a group costs only the lanes that reach it, and a sweep at configs 4 and 5 and
+// the sub-pixel scene put the best threshold near 5 (it was 21 for the walk of every
+// reached group by the whole wave).
+constexpr int kBoxPerGroup = 5;
 
 // Groups of a pair window: their pixel constants are staged together in a wave's slice,
 // kSlot entries apart (one more than a group's 64 pixels), so that lanes reading the
