@@ -52,9 +52,14 @@ def kernel_source_hash(kname):
 
 def committed_traffic(kname, tile, batch):
     """HBM bytes per launch of `kname` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (profiles/<kname>_traffic.txt), or None when there is none for this tiling or
-    the kernel's sources have changed since the counters were taken."""
+    summary (profiles/<kname>_traffic.txt, or profiles/<kname>_traffic_batch<B>.txt for
+    the forward at another LDS batch), or None when there is none for this tiling or the
+    kernel's sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kname}_traffic.txt")
+    if kname == "k_raster_fwd":
+        per_batch = os.path.join(ROOT, "profiles", f"{kname}_traffic_batch{batch}.txt")
+        if os.path.exists(per_batch):
+            path = per_batch
     if not os.path.exists(path):
         return None
     fields = {}
@@ -244,7 +249,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
     log(f"{name}: timing {steps} {'eager steps' if eager else 'graph replays'}")
     def timed_window():
         """`steps` timed steps; per step its time, label changes and the counters."""
-        w = {k: [] for k in ("ms", "deltas", "entries", "pairs", "evals", "chunks", "boxes")}
+        w = {k: [] for k in ("ms", "deltas", "entries", "pairs", "evals", "chunks", "boxes", "waves")}
         for _ in range(steps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -255,13 +260,13 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
             if not t.dense:
                 w["deltas"].append(int(t.n_delta.item()))
             c = t.r.counters()
-            for key, x in zip(("entries", "pairs", "evals", "chunks", "boxes"), c):
+            for key, x in zip(("entries", "pairs", "evals", "chunks", "boxes", "waves"), c):
                 w[key].append(x)
         return w
 
     win = timed_window()
-    step_ms, pairs, evals, entries, chunks, boxes = (win[k] for k in ("ms", "pairs", "evals", "entries", "chunks",
-                                                                      "boxes"))
+    step_ms, pairs, evals, entries, chunks, boxes, waves = (win[k] for k in ("ms", "pairs", "evals", "entries",
+                                                                             "chunks", "boxes", "waves"))
     deltas = win["deltas"]
     # kernel timing pass: eager steps with kernel-bracketing events, and the pair
     # counters of the same launches
@@ -316,6 +321,7 @@ def run_form(scene, dense, steps, warmup, fraction, tile, batch, tune, eager=Fal
         "entries": statistics.mean(entries),
         "chunks": statistics.mean(chunks),
         "box_items": statistics.mean(boxes),
+        "wave_items": statistics.mean(waves),
         "loss": loss,
         "active": t.k,
         "tile": t.r.tuning.tile,
@@ -698,6 +704,7 @@ def main():
         "active": {"ms_per_step": round(act["ms_per_step"], 4), "ms_median": round(act["ms_per_step_median"], 4),
                    "evals_per_s": value, "contributing_pairs": act["pairs"], "evaluated_pairs": act["evals"],
                    "tile_entries": act["entries"], "bwd_work_items": act["chunks"], "bwd_box_items": act["box_items"],
+                   "bwd_wave_items": act["wave_items"],
                    "raster_fwd_ms": round(act["raster_fwd_ms"], 4), "raster_bwd_ms": round(act["raster_bwd_ms"], 4),
                    "label_changes_per_step": {"mean": round(statistics.mean(act["label_changes"]), 1),
                                               "min": min(act["label_changes"]), "max": max(act["label_changes"])},
@@ -712,7 +719,7 @@ def main():
                          "evals_per_s": dense["pairs"] / (dense["ms_per_step"] * 1e-3),
                          "contributing_pairs": dense["pairs"], "evaluated_pairs": dense["evals"],
                          "tile_entries": dense["entries"], "bwd_work_items": dense["chunks"],
-                         "bwd_box_items": dense["box_items"],
+                         "bwd_box_items": dense["box_items"], "bwd_wave_items": dense["wave_items"],
                          "raster_fwd_ms": round(dense["raster_fwd_ms"], 4),
                          "raster_bwd_ms": round(dense["raster_bwd_ms"], 4),
                          "stages": stage_roofs(dense, scene.n, nv, px, True)}

@@ -427,7 +427,7 @@ oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_st
 
 /*
  * Wait for `stream` and copy the counters the last oit_render_fwd / oit_render_bwd on
- * this workspace left (arguments as given to that call; out (host) [5]):
+ * this workspace left (arguments as given to that call; out (host) [6]):
  *   out[0] (tile, splat) entries the forward needed (also when it overflowed
  *          tuning.pair_capacity, so a caller can size pair_capacity and run again;
  *          saturated at 2^32 - 1, above any pair capacity),
@@ -435,7 +435,10 @@ oit_status oit_read_status(const void *ws, size_t ws_bytes, int32_t *out, oit_st
  *   out[2] active (splat, pixel) pairs it evaluated (tile entries x in-image tile pixels),
  *   out[3] backward work items (up to 64 active entries of one tile each),
  *   out[4] of those, the items the last backward walked footprint box by footprint box
- *          (small footprints) instead of pixel group by pixel group.
+ *          (small footprints) instead of pixel group by pixel group,
+ *   out[5] of those, the items whose pixel groups the whole wave walked one by one
+ *          (footprints that nearly all reach all the item's groups); the rest had their
+ *          (entry, group) pairs dealt to the lanes.
  */
 oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity *cap,
                              const oit_camera *cams, int32_t n_views, const oit_tuning *tuning,

@@ -347,10 +347,11 @@ __device__ __forceinline__ void write_partials(float *dst, float qa, float qb, f
 }
 
 template <int S>
-// boxed: the wave's count of items walked box by box (for the counters)
+// walks: the wave's counts of items walked box by box (low 16 bits) and group by group by
+// the whole wave (high 16 bits), for the counters
 __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wave, int lane,
                                          float4 (*s_c)[kWin * kSlot], float2 (*s_B)[kWin * kSlot],
-                                         uint8_t (*s_pair)[kWin * 64], uint32_t &boxed)
+                                         uint8_t (*s_pair)[kWin * 64], uint32_t &walks)
 {
     constexpr int GX = S / kGroup;   // groups per tile edge
     const uint64_t cap = (uint64_t)b.pair_cap;
@@ -433,7 +434,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         int amax = area;
         for (int m = 32; m > 0; m >>= 1) amax = max(amax, __shfl_xor(amax, m));
         if (amax <= kBoxPerGroup * __builtin_popcount(mask)) {
-            ++boxed;
+            ++walks;
             BwdSums o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             int c = bc0, r = br0;
             // the constants of the lane's next box pixel are fetched one pixel ahead
@@ -521,6 +522,7 @@ __device__ __forceinline__ void bwd_item(const Buffers &b, uint32_t item, int wa
         }
     }
     if (10 * rounds >= 9 * __builtin_popcount(mask)) {
+        walks += 1u << 16;
         uint32_t rest = mask;
         int g = __builtin_ctz(rest);
         rest &= rest - 1;
@@ -673,7 +675,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const uint32_t want = 64u * ((per_tile + 5u) / 6u);
     int lb = 6;
     while ((1u << lb) < want && lb < 10) ++lb;
-    uint32_t boxed = 0;
+    uint32_t walks = 0;   // a wave takes far fewer than 2^16 items
     for (;;) {
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(&a.b.counters[CNT_XQUEUE + xcd], 1u);
@@ -681,15 +683,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         // the ticket-th item of this XCD: block xcd + 8 (ticket / B), offset ticket % B
         const uint64_t item = (((uint64_t)xcd + (uint64_t)kXcds * (ticket >> lb)) << lb) + (ticket & ((1u << lb) - 1u));
         if (item >= total) break;   // items grow with the ticket: the queue is drained
-        bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, s_pair, boxed);
+        bwd_item<S>(a.b, (uint32_t)item, wave, lane, s_c, s_B, s_pair, walks);
     }
-    // one atomic per block for the box-walk counter
-    __shared__ uint32_t s_boxed[4];
-    if (lane == 0) s_boxed[wave] = boxed;
+    // one atomic per block for each walk counter
+    __shared__ uint32_t s_walks[4];
+    if (lane == 0) s_walks[wave] = walks;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t n = s_boxed[0] + s_boxed[1] + s_boxed[2] + s_boxed[3];
-        if (n) atomicAdd(&a.b.counters[CNT_BOX_ITEMS], n);
+        uint32_t nb = 0, nw = 0;
+        for (int k = 0; k < 4; ++k) {
+            nb += s_walks[k] & 0xffffu;
+            nw += s_walks[k] >> 16;
+        }
+        if (nb) atomicAdd(&a.b.counters[CNT_BOX_ITEMS], nb);
+        if (nw) atomicAdd(&a.b.counters[CNT_WAVE_ITEMS], nw);
     }
 }
 

@@ -552,8 +552,10 @@ oit_status oit_render_bwd(const oit_splats *splats, const float *sigma, const fl
     const GradPtrs g{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->vsh,
                      grads->stride};
     upload_cams(p.cams_host, n_views, b.cams, s);
-    fill_u32(b.counters + CNT_XQUEUE, kXcds, 0u, s);
-    fill_u32(b.counters + CNT_BOX_ITEMS, 1, 0u, s);
+    // the backward's queues and walk counters in one fill (the forward's ticket among them
+    // is reset again by the next forward's ordering kernel)
+    static_assert(CNT_XQUEUE + kXcds == CNT_BOX_ITEMS && CNT_WAVE_ITEMS > CNT_BOX_ITEMS, "counter slots");
+    fill_u32(b.counters + CNT_XQUEUE, CNT_WAVE_ITEMS + 1 - CNT_XQUEUE, 0u, s);
     auto mark = [&](int k) {
         if (g_timing_on) (void)hipEventRecord(g_ev[k], s);
     };
@@ -833,6 +835,7 @@ oit_status oit_read_counters(const void *ws, size_t ws_bytes, const oit_capacity
     out[2] = (int64_t)((uint64_t)v[CNT_EVAL] | ((uint64_t)v[CNT_EVAL + 1] << 32));
     out[3] = (int64_t)v[CNT_TOTAL_CHUNKS];
     out[4] = (int64_t)v[CNT_BOX_ITEMS];
+    out[5] = (int64_t)v[CNT_WAVE_ITEMS];
     return ok();
 }
 

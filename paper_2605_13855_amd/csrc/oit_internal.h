@@ -31,8 +31,9 @@ constexpr int kSigPreParts = 4096;             // blocks of the preprocess backw
 // CNT_XQUEUE .. CNT_XQUEUE + 7: the backward's per-XCD work-queue tickets
 // CNT_BOX_ITEMS: backward work items that took the footprint-box walk
 // CNT_FQUEUE: the forward's work-queue ticket (positions in the heavy-first tile order)
+// CNT_WAVE_ITEMS: backward work items walked group by group by the whole wave
 enum { CNT_NPAIRS = 0, CNT_TOTAL_CHUNKS = 1, CNT_TOTAL_ENTRIES = 2, CNT_SORT_N = 3, CNT_PAIRS = 4, CNT_EVAL = 6, CNT_CAP = 8,
-       CNT_XQUEUE = 9, CNT_BOX_ITEMS = 17, CNT_FQUEUE = 18, CNT_SLOTS = 32 };
+       CNT_XQUEUE = 9, CNT_BOX_ITEMS = 17, CNT_FQUEUE = 18, CNT_WAVE_ITEMS = 19, CNT_SLOTS = 32 };
 constexpr int kXcds = 8;        // XCDs of the device; workgroup b runs on XCD b mod 8
 
 struct SplatPtrs {

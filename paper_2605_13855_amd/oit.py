@@ -292,8 +292,9 @@ def read_status(ws, stream=None) -> int:
 
 def read_counters(ws, cap: Capacity, cams_arr, n_views, tuning: Tuning, stream=None):
     """(entries needed, contributing pairs, evaluated pairs, backward work items, items the
-    backward walked box by box) of the last forward / backward on this workspace."""
-    out = (ctypes.c_int64 * 5)()
+    backward walked box by box, items it walked group by group with the whole wave) of the
+    last forward / backward on this workspace."""
+    out = (ctypes.c_int64 * 6)()
     rc = lib.oit_read_counters(_ptr(ws), ws.numel(), ctypes.byref(cap), cams_arr, n_views, ctypes.byref(tuning),
                                out, _stream(stream))
     _check(rc, "oit_read_counters")

@@ -102,19 +102,35 @@ def backward_walk_counts(sc, tile=16):
                torch.zeros(1, dtype=torch.float64, device=DEV))
     torch.cuda.synchronize()
     c = r.counters()
-    return c[3], c[4]
+    return c[3], c[4], c[5]
 
 
-def test_backward_walks_both_ways():
-    """The backward walks small footprints box by box and large ones group by group; the
-    config-1 parity cases at tile 16 contain work items of both kinds, the sub-pixel
-    case below almost only box walks."""
-    items, boxed = backward_walk_counts(scenes.make_scene(1))
-    log(f"  config 1: {items} backward work items, {boxed} walked box by box")
-    assert 0 < boxed < items
-    items, boxed = backward_walk_counts(scenes.make_scene(1, log_scale_mu=-6.0))
-    log(f"  config 1, sub-pixel splats: {items} backward work items, {boxed} walked box by box")
+def test_backward_walks_three_ways():
+    """The backward walks the smallest footprints box by box; of the other work items,
+    those whose splats nearly all reach all the item's pixel groups are walked group by
+    group by the whole wave, and the rest by (entry, group) pairs dealt to the lanes.  The
+    config-1 scenes of the parity cases (sub-pixel, default and large splats) take all
+    three walks between them, the sub-pixel one mostly the box walk."""
+    counts = {}
+    for name, mu in (("sub-pixel", -6.0), ("default", -3.5), ("large", -2.5)):
+        items, boxed, waved = backward_walk_counts(scenes.make_scene(1, log_scale_mu=mu))
+        log(f"  config 1, {name} splats: {items} backward work items, {boxed} walked box by box, "
+            f"{waved} group by group by the whole wave, {items - boxed - waved} by dealt pairs")
+        assert 0 <= boxed and 0 <= waved and boxed + waved <= items
+        counts[name] = (items, boxed, waved)
+    items, boxed, _ = counts["sub-pixel"]
     assert boxed > items // 2
+    assert any(w > 0 for _, _, w in counts.values())
+    assert any(i - b - w > 0 for i, b, w in counts.values())
+
+
+def test_large_splat_parity():
+    """Splats large against the tile (log-scale ~ N(-2.5, 0.3)): most backward work items
+    have nearly every splat reach every pixel group, the case walked group by group by the
+    whole wave."""
+    for tile in (16, 32):
+        log(f"large splats, tile {tile}")
+        dense_case(scenes.make_scene(1, log_scale_mu=-2.5), tile=tile, batch=64)
 
 
 def test_subpixel_scene_parity():
