@@ -1366,7 +1366,8 @@ __device__ __forceinline__ void fwd_tiles(const FwdArgs &a, FwdShared<S, BATCH, 
         if (ticket >= (uint32_t)a.b.T) break;
         // Nothing derived from the thread index or the arguments is kept across tiles
         // (it would hold registers through the blending loops): both are taken afresh
-        // for every tile, the arguments by scalar loads from their segment.
+        // for every tile, the arguments by scalar loads from their segment (k_raster_fwd
+        // takes one argument, the FwdArgs, which therefore starts the segment).
         int tid = (int)threadIdx.x;
         asm volatile("" : "+v"(tid));
         typedef const __attribute__((address_space(4))) char *KernArg;
