@@ -129,12 +129,22 @@ struct PreArgs {
     Buffers b;
 };
 
-// t: record index; pv: the (listed record, view) pair's index view * nrec + k
-__device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
+// What the tile count of one (record, view) pair takes: the record's exponent form
+// (mx, my, qa, qb, qc of the record), the test's bound, the tile rectangle and the view.
+struct CountItem {
+    float mx, my, qa, qb, qc, tau, lo;
+    int org;    // rectangle origin: x | y << 16
+    int wv;     // rectangle width | view << 16
+    int area;   // tiles of the rectangle (0: nothing to count)
+};
+
+// t: record index; v: view.  Writes the record and its tile rectangle; returns false
+// if the record is unused in this call.
+__device__ bool preprocess_one(const PreArgs &a, int64_t t, int v, CountItem &ci)
 {
     int sign = 0;
     const int64_t id = record_row(a.rl, t, sign);
-    if (id < 0) return;
+    if (id < 0) return false;
     const SplatPtrs &sp = sign == 0 ? a.sp : a.dsp;
     const CamDev &cam = a.b.cams[v];
     const size_t ri = (size_t)v * a.rl.Rcap + t;
@@ -159,7 +169,6 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
 
     Rec r;
     short4 rect = make_short4(0, 0, 0, 0);
-    uint32_t hits = 0;
     Geo g;
     if (geometry(cam, mu, S6, g)) {
         const float lo = -log2f(1.f + expf(-sp.logit[id]));   // log2(sigmoid(logit))
@@ -225,13 +234,11 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
             if (x0 <= x1 && y0 <= y1) {
                 const int S = a.b.tile;
                 rect = make_short4((short)(x0 / S), (short)(x1 / S + 1), (short)(y0 / S), (short)(y1 / S + 1));
-                for (int ty = rect.z; ty < rect.w; ++ty)
-                    for (int tx = rect.x; tx < rect.y; ++tx)
-                        if (tile_hit(r, tau, cam, S, tx, ty)) ++hits;
+                const int rw = rect.y - rect.x;
+                ci = CountItem{r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, tau, lo, (int)rect.x | ((int)rect.z << 16),
+                               rw | (v << 16), rw * (rect.w - rect.z)};
             }
         }
-        // the raster forward clamps alpha at the cap only if some listed record can reach it
-        if (hits && lo > kLog2NoCap) atomicOr(&a.b.counters[CNT_CAP], 1u);
     } else {
         r.a = make_float4(0.f, 0.f, 0.f, 0.f);
         r.b = make_float4(0.f, -1e30f, 0.f, 0.f);
@@ -242,10 +249,57 @@ __device__ void preprocess_one(const PreArgs &a, int64_t t, int v, size_t pv)
     dst.b = r.b;
     dst.c = r.c;
     a.b.rect[ri] = rect;
-    a.b.nhits[pv] = hits;
+    return true;
 }
 
-__global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
+// Tiles of each lane's rectangle that its record reaches (tile_hit), counted by the
+// whole wave: the 64 rectangles are laid end to end (lane order, tile rows within a
+// rectangle) and the wave tests 64 consecutive tiles of that sequence per round, each
+// lane taking the values of the tile's owner from the owner's lane; an owner adds the
+// round's hits in its own stretch of the sequence.  (The rectangles differ widely in
+// size, so a lane walking its own would keep the wave as long as its largest.)
+__device__ uint32_t wave_count_hits(const CountItem &ci, const CamDev *cams, int S)
+{
+    const int lane = threadIdx.x & 63;
+    int incl = ci.area;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int excl = incl - ci.area, total = __shfl(incl, 63);
+    uint32_t hits = 0;
+    for (int f0 = 0; f0 < total; f0 += 64) {
+        const int f = f0 + lane;
+        // owner of position f: the last lane whose rectangle starts at or before f
+        int p = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int e = __shfl(excl, p + step);
+            if (e <= f) p += step;
+        }
+        const int j = f - __shfl(excl, p);
+        const int porg = __shfl(ci.org, p), pwv = __shfl(ci.wv, p);
+        Rec r{};
+        r.a = make_float4(__shfl(ci.mx, p), __shfl(ci.my, p), __shfl(ci.qa, p), __shfl(ci.qb, p));
+        r.b.x = __shfl(ci.qc, p);
+        const float ptau = __shfl(ci.tau, p);
+        bool hit = false;
+        if (f < total) {
+            const uint32_t w = (uint32_t)(pwv & 0xffff);
+            const int ty = (porg >> 16) + (int)((uint32_t)j / w), tx = (porg & 0xffff) + (int)((uint32_t)j % w);
+            hit = tile_hit(r, ptau, cams[pwv >> 16], S, tx, ty);
+        }
+        const uint64_t hb = __ballot(hit);
+        const int s0 = max(excl - f0, 0), s1 = min(excl + ci.area - f0, 64);
+        if (s1 > s0) {
+            const uint64_t m = s1 - s0 == 64 ? ~0ull : ((1ull << (s1 - s0)) - 1ull) << s0;
+            hits += (uint32_t)__builtin_popcountll(hb & m);
+        }
+    }
+    return hits;
+}
+
+// Four waves per SIMD: the projection and colour terms fit in 128 registers without spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess_count(PreArgs a)
 {
     const int V = a.b.n_views;
     const RecItems it = rec_items(a.rl, V);
@@ -254,8 +308,16 @@ __global__ __launch_bounds__(256) void k_preprocess_count(PreArgs a)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t k = i / V;
     int v = (int)(i % V);
-    for (; i < it.total; i += stride) {
-        preprocess_one(a, rec_of(a.rl, it.na, k), v, (size_t)v * it.nrec + k);
+    // a wave's 64 items are consecutive, so the loop is uniform over the wave
+    for (; i - (threadIdx.x & 63) < it.total; i += stride) {
+        CountItem ci{};
+        const bool listed = i < it.total && preprocess_one(a, rec_of(a.rl, it.na, k), v, ci);
+        const uint32_t hits = wave_count_hits(ci, a.b.cams, a.b.tile);
+        if (listed) {
+            a.b.nhits[(size_t)v * it.nrec + k] = hits;
+            // the raster forward clamps alpha at the cap only if some listed record can reach it
+            if (hits && ci.lo > kLog2NoCap) atomicOr(&a.b.counters[CNT_CAP], 1u);
+        }
         k += sk;
         v += (int)sv;
         if (v >= V) {
@@ -620,113 +682,129 @@ __global__ void k_list_total(ListArgs a)
     if (E > cap) atomicOr(a.b.status, OIT_STATUS_PAIR_OVERFLOW);
 }
 
-// STAGED: the entries go to the wave's LDS slice at (slot - base) and the wave writes
-// them out afterwards; otherwise straight to the list.
-template <bool STAGED>
-__device__ void list_one(const ListArgs &a, int64_t t, int v, size_t pv, uint32_t *sk, uint32_t *sr, uint64_t base)
+// Sort key of a tile entry: (tile, class) and a size class, 3 log2 of the pixel count of
+// the footprint box (half-extents hx, hy around the mean mx, my; hx < 0: none) inside the
+// tile, so that a 64-entry backward chunk holds footprints of similar size.
+__device__ __forceinline__ uint32_t entry_key(const CamDev &cam, int S, int tx, int ty, uint32_t cls, float mx,
+                                              float my, float hx, float hy)
 {
-    int sign = 0;
-    if (record_row(a.rl, t, sign) < 0) return;
-    const uint32_t nh = a.b.nhits[pv];
-    if (nh == 0) return;
-    const CamDev &cam = a.b.cams[v];
-    const size_t ri = (size_t)v * a.rl.Rcap + t;
-    const short4 rect = a.b.rect[ri];
+    const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
+    uint32_t sc = 0;
+    if (hx >= 0.f) {
+        const float dx0 = (float)(tx * S) + 0.5f - mx, dy0 = (float)(ty * S) + 0.5f - my;
+        const float lim = 1e6f;
+        const int c0 = max(0, (int)ceilf(fmaxf(-hx - dx0, -lim)));
+        const int c1 = min(min(S, cam.W - tx * S) - 1, (int)floorf(fminf(hx - dx0, lim)));
+        const int r0 = max(0, (int)ceilf(fmaxf(-hy - dy0, -lim)));
+        const int r1 = min(min(S, cam.H - ty * S) - 1, (int)floorf(fminf(hy - dy0, lim)));
+        const int area = (c1 >= c0 && r1 >= r0) ? (c1 - c0 + 1) * (r1 - r0 + 1) : 0;
+        if (area > 1) sc = min((1u << kSizeBits) - 1u, (uint32_t)(3.f * log2f((float)area)));
+    }
+    return ((tile * 2u + cls) << kSizeBits) | sc;
+}
+
+// View-major items: a wave takes 64 consecutive (record, view) pairs, whose slots form
+// one contiguous range.  Their tile rectangles differ widely in size (at the benchmark
+// scenes a wave's largest is about three times their mean), so the lanes do not walk
+// their own rectangles: the wave lays the 64 rectangles end to end (pair order, tile
+// rows within a rectangle, the count's order) and tests 64 consecutive tiles of that
+// sequence per round, each lane taking the pair values of the tile's owner from the
+// owner's lane.  A hit's slot is the wave's first slot plus the hits before it in the
+// sequence, so a round stores its hits as one contiguous run.
+__global__ __launch_bounds__(256) void k_list(ListArgs a)
+{
+    const int V = a.b.n_views;
+    const RecItems it = rec_items(a.rl, V);
+    const int lane = threadIdx.x & 63;
     const int S = a.b.tile;
     const uint64_t cap = (uint64_t)a.b.pair_cap;
-    const Rec r = a.b.rec[ri];
-    const float tau = tile_tau(r.b.y);
-    const uint32_t cls = sign == 0 ? 0u : 1u;
-    // half-extents of the widened alpha >= 1/255 box (the backward's, same formulas)
-    float hx = -1.f, hy = -1.f;
-    {
-        const float A = -r.a.z, B = -0.5f * r.a.w, C = -r.b.x;
-        const float det = A * C - B * B;
-        const float tb = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
-        if (tb > 0.f && det > 0.f) {
-            hx = sqrtf(tb * C / det) + 0.01f;
-            hy = sqrtf(tb * A / det) + 0.01f;
-        }
-    }
-    const bool zero_ep = sign == 0 && a.b.bwd_mode == OIT_BWD_PER_PIXEL;
-    // the pair's k-th tile hit takes slot hoff + k (same tile order as the count)
-    uint64_t o = a.b.hoff[pv];
-    for (int ty = rect.z; ty < rect.w; ++ty)
-        for (int tx = rect.x; tx < rect.y; ++tx) {
-            if (!tile_hit(r, tau, cam, S, tx, ty)) continue;
-            if (o < cap) {
-                const uint32_t tile = (uint32_t)(cam.tile_base + ty * cam.tiles_x + tx);
-                uint32_t key;
-                // size class: 3 log2 of the box's pixel count inside the tile, so that
-                // a 64-entry backward chunk holds footprints of similar size
-                uint32_t sc = 0;
-                if (hx >= 0.f) {
-                    const float dx0 = (float)(tx * S) + 0.5f - r.a.x, dy0 = (float)(ty * S) + 0.5f - r.a.y;
-                    const float lim = 1e6f;
-                    const int c0 = max(0, (int)ceilf(fmaxf(-hx - dx0, -lim)));
-                    const int c1 = min(min(S, cam.W - tx * S) - 1, (int)floorf(fminf(hx - dx0, lim)));
-                    const int r0 = max(0, (int)ceilf(fmaxf(-hy - dy0, -lim)));
-                    const int r1 = min(min(S, cam.H - ty * S) - 1, (int)floorf(fminf(hy - dy0, lim)));
-                    const int area = (c1 >= c0 && r1 >= r0) ? (c1 - c0 + 1) * (r1 - r0 + 1) : 0;
-                    if (area > 1) sc = min((1u << kSizeBits) - 1u, (uint32_t)(3.f * log2f((float)area)));
+    const bool per_pixel = a.b.bwd_mode == OIT_BWD_PER_PIXEL;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; i0 < it.total;
+         i0 += (int64_t)gridDim.x * 256) {
+        const int64_t i = i0 + lane;
+        // the lane's own pair: rectangle origin (x | y << 16), width | class << 15 |
+        // view << 16, record, tile-test form and footprint box
+        int area = 0, org = 0, wcv = 0;
+        uint32_t rec = 0;
+        float mx = 0.f, my = 0.f, qa = 0.f, qb = 0.f, qc = 0.f, tau = 0.f, hx = -1.f, hy = -1.f;
+        if (i < it.total) {
+            const int v = (int)(i / it.nrec);
+            const int64_t t = rec_of(a.rl, it.na, i - (int64_t)v * it.nrec);
+            int sign = 0;
+            if (record_row(a.rl, t, sign) >= 0 && a.b.nhits[i] != 0) {
+                const size_t ri = (size_t)v * a.rl.Rcap + t;
+                const short4 rect = a.b.rect[ri];
+                const Rec r = a.b.rec[ri];
+                mx = r.a.x;
+                my = r.a.y;
+                qa = r.a.z;
+                qb = r.a.w;
+                qc = r.b.x;
+                tau = tile_tau(r.b.y);
+                // half-extents of the widened alpha >= 1/255 box (the backward's, same formulas)
+                const float A = -qa, B = -0.5f * qb, C = -qc;
+                const float det = A * C - B * B;
+                const float tb = (r.b.y - kLog2AlphaMin) * 1.001f + 1e-3f;
+                if (tb > 0.f && det > 0.f) {
+                    hx = sqrtf(tb * C / det) + 0.01f;
+                    hy = sqrtf(tb * A / det) + 0.01f;
                 }
-                key = ((tile * 2u + cls) << kSizeBits) | sc;
-                if constexpr (STAGED) {
-                    sk[o - base] = key;
-                    sr[o - base] = (uint32_t)t;
-                } else {
+                const int w = rect.y - rect.x;
+                area = w * (rect.w - rect.z);
+                org = (int)rect.x | ((int)rect.z << 16);
+                wcv = w | ((sign == 0 ? 0 : 1) << 15) | (v << 16);
+                rec = (uint32_t)t;
+            }
+        }
+        // the lane's rectangle starts at position excl of the wave's sequence
+        int incl = area;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int excl = incl - area, total = __shfl(incl, 63);
+        uint64_t slot = a.b.hoff[i0];
+        for (int f0 = 0; f0 < total; f0 += 64) {
+            const int f = f0 + lane;
+            // owner of position f: the last lane whose rectangle starts at or before f
+            // (it has a nonempty rectangle when f < total)
+            int p = 0;
+            for (int step = 32; step > 0; step >>= 1) {
+                const int e = __shfl(excl, p + step);
+                if (e <= f) p += step;
+            }
+            const int j = f - __shfl(excl, p);
+            const int porg = __shfl(org, p), pwcv = __shfl(wcv, p);
+            const uint32_t prec = (uint32_t)__shfl((int)rec, p);
+            Rec r{};
+            r.a = make_float4(__shfl(mx, p), __shfl(my, p), __shfl(qa, p), __shfl(qb, p));
+            r.b.x = __shfl(qc, p);
+            const float ptau = __shfl(tau, p), phx = __shfl(hx, p), phy = __shfl(hy, p);
+            bool hit = false;
+            uint32_t key = 0, cls = 0;
+            if (f < total) {
+                const uint32_t w = (uint32_t)(pwcv & 0x7fff);
+                cls = (uint32_t)(pwcv >> 15) & 1u;
+                const CamDev &cam = a.b.cams[pwcv >> 16];
+                const int ty = (porg >> 16) + (int)((uint32_t)j / w), tx = (porg & 0xffff) + (int)((uint32_t)j % w);
+                hit = tile_hit(r, ptau, cam, S, tx, ty);
+                if (hit) key = entry_key(cam, S, tx, ty, cls, r.a.x, r.a.y, phx, phy);
+            }
+            const uint64_t hb = __ballot(hit);
+            if (hit) {
+                const uint64_t o = slot + (uint64_t)__builtin_popcountll(hb & lt);
+                if (o < cap) {
                     a.b.keys[0][o] = key;
                     a.b.vals[0][o] = (uint32_t)o;
-                    a.b.recs[0][o] = (uint32_t)t;
-                    if (zero_ep) {
-                        float4 *e = (float4 *)(a.b.ep + o * kEpStride);
-                        e[0] = e[1] = e[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    a.b.recs[0][o] = prec;
+                    if (per_pixel && cls == 0u) {
+                        float4 *ep = (float4 *)(a.b.ep + o * kEpStride);
+                        ep[0] = ep[1] = ep[2] = make_float4(0.f, 0.f, 0.f, 0.f);
                     }
                 }
             }
-            ++o;
-        }
-}
-
-// View-major items: the 64 lanes of a wave take 64 consecutive (record, view) pairs,
-// whose slots form one contiguous range.  When the range fits the wave's LDS slice,
-// the lanes put their entries there and the wave writes the range out in order (one
-// 256-byte run per store instead of 64 scattered words); a larger range is written
-// directly.
-constexpr int kListStage = 1024;
-
-__global__ __launch_bounds__(256) void k_list(ListArgs a)
-{
-    __shared__ uint32_t s_key[4][kListStage], s_rec[4][kListStage];
-    const int V = a.b.n_views;
-    const RecItems it = rec_items(a.rl, V);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t cap = (uint64_t)a.b.pair_cap;
-    const bool per_pixel = a.b.bwd_mode == OIT_BWD_PER_PIXEL;
-    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 64; i0 < it.total; i0 += (int64_t)gridDim.x * 256) {
-        const int64_t i = i0 + lane;
-        const int64_t last = i0 + 63 < it.total ? i0 + 63 : it.total - 1;
-        const uint64_t base = a.b.hoff[i0], end = (uint64_t)a.b.hoff[last] + a.b.nhits[last];
-        const int v = (int)(i / it.nrec);
-        const int64_t k = i - (int64_t)v * it.nrec;
-        if (end - base <= (uint64_t)kListStage) {
-            if (i < it.total) list_one<true>(a, rec_of(a.rl, it.na, k), v, (size_t)i, s_key[wave], s_rec[wave], base);
-            __builtin_amdgcn_wave_barrier();
-            for (uint64_t e = lane; e < end - base; e += 64) {
-                const uint64_t o = base + e;
-                if (o >= cap) break;
-                const uint32_t key = s_key[wave][e];
-                a.b.keys[0][o] = key;
-                a.b.vals[0][o] = (uint32_t)o;
-                a.b.recs[0][o] = s_rec[wave][e];
-                if (per_pixel && ((key >> kSizeBits) & 1u) == 0u) {
-                    float4 *ep = (float4 *)(a.b.ep + o * kEpStride);
-                    ep[0] = ep[1] = ep[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        } else if (i < it.total) {
-            list_one<false>(a, rec_of(a.rl, it.na, k), v, (size_t)i, nullptr, nullptr, 0);
+            slot += (uint64_t)__builtin_popcountll(hb);
         }
     }
 }
@@ -805,59 +883,91 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const 
     __syncthreads();
     uint64_t lo, hi;
     sort_range(*nptr, lo, hi);
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256)
-        atomicAdd(&h[(keys[i] >> shift) & (kRadixBuckets - 1u)], 1u);
+    // four keys per thread in flight before their counts
+    for (uint64_t b0 = lo; b0 < hi; b0 += 1024) {
+        uint32_t k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = b0 + u * 256 + threadIdx.x;
+            k[u] = i < hi ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (b0 + u * 256 + threadIdx.x < hi) atomicAdd(&h[(k[u] >> shift) & (kRadixBuckets - 1u)], 1u);
+    }
     __syncthreads();
     if (threadIdx.x < kRadixBuckets) hist[(size_t)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter each block's keys to their digit's range in key order: rounds of 256 keys in
-// index order; within a round a key's rank among equal digits comes from ballots over
-// the digit's bits (in-wave) and the per-wave counts of lower waves (LDS).
+// Scatter each block's keys to their digit's range in key order, in rounds of 1024
+// keys in index order (four per thread, loaded together so that a round's loads are in
+// flight at once).  A key's rank among the equal digits of its wave comes from ballots
+// over the digit's bits; the first position of each (key of the thread, wave) group
+// per digit from a scan of the groups' counts in LDS.  The counts and the positions
+// have arrays of their own, so a round needs two barriers: the scan clears the counts
+// it has read, and the next round's counts are written after the barrier that
+// precedes this round's scatter.
+constexpr int kScatterPer = 4;
+
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
                                                        const uint32_t *recs_in, uint32_t *keys_out,
                                                        uint32_t *vals_out, uint32_t *recs_out, const uint32_t *nptr,
                                                        int shift, const uint32_t *hist_off)
 {
+    constexpr int kSub = kScatterPer * 4;   // groups of a round, in index order: (u, wave)
     __shared__ uint32_t run[kRadixBuckets];
-    __shared__ uint32_t wc[4][kRadixBuckets];
+    __shared__ uint32_t cnt[kSub][kRadixBuckets], first[kSub][kRadixBuckets];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid < kRadixBuckets) {
-        run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
-        for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
-    }
+    if (tid < kRadixBuckets) run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
+    for (int e = tid; e < kSub * kRadixBuckets; e += 256) (&cnt[0][0])[e] = 0;
     __syncthreads();
     uint64_t lo, hi;
     sort_range(*nptr, lo, hi);
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint64_t base = lo; base < hi; base += 256) {
-        const uint64_t i = base + tid;
-        const bool valid = i < hi;
-        const uint32_t key = valid ? keys_in[i] : 0u, val = valid ? vals_in[i] : 0u, rec = valid ? recs_in[i] : 0u;
-        const uint32_t d = (key >> shift) & (kRadixBuckets - 1u);
-        uint64_t peers = __ballot(valid);
+    for (uint64_t base = lo; base < hi; base += kScatterPer * 256) {
+        uint32_t key[kScatterPer], val[kScatterPer], rec[kScatterPer], d[kScatterPer], rank[kScatterPer];
+        bool valid[kScatterPer];
 #pragma unroll
-        for (int bit = 0; bit < kRadixBits; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            const uint64_t bb = __ballot(set);
-            peers &= set ? bb : ~bb;
+        for (int u = 0; u < kScatterPer; ++u) {
+            const uint64_t i = base + u * 256 + tid;
+            valid[u] = i < hi;
+            key[u] = valid[u] ? keys_in[i] : 0u;
+            val[u] = valid[u] ? vals_in[i] : 0u;
+            rec[u] = valid[u] ? recs_in[i] : 0u;
         }
-        const uint32_t rank = (uint32_t)__builtin_popcountll(peers & lt);
-        if (valid && rank == 0) wc[wave][d] = (uint32_t)__builtin_popcountll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wc[w][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
-            recs_out[pos] = rec;
+#pragma unroll
+        for (int u = 0; u < kScatterPer; ++u) {
+            d[u] = (key[u] >> shift) & (kRadixBuckets - 1u);
+            uint64_t peers = __ballot(valid[u]);
+#pragma unroll
+            for (int bit = 0; bit < kRadixBits; ++bit) {
+                const bool set = (d[u] >> bit) & 1u;
+                const uint64_t bb = __ballot(set);
+                peers &= set ? bb : ~bb;
+            }
+            rank[u] = (uint32_t)__builtin_popcountll(peers & lt);
+            if (valid[u] && rank[u] == 0) cnt[u * 4 + wave][d[u]] = (uint32_t)__builtin_popcountll(peers);
         }
         __syncthreads();
         if (tid < kRadixBuckets) {
-            run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-            for (int w = 0; w < 4; ++w) wc[w][tid] = 0;
+            uint32_t pos = run[tid];
+            for (int g = 0; g < kSub; ++g) {
+                const uint32_t c = cnt[g][tid];
+                cnt[g][tid] = 0;
+                first[g][tid] = pos;
+                pos += c;
+            }
+            run[tid] = pos;
         }
         __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kScatterPer; ++u)
+            if (valid[u]) {
+                const uint32_t pos = first[u * 4 + wave][d[u]] + rank[u];
+                keys_out[pos] = key[u];
+                vals_out[pos] = val[u];
+                recs_out[pos] = rec[u];
+            }
     }
 }
 
