@@ -902,12 +902,13 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t *keys, const 
 // Scatter each block's keys to their digit's range in key order, in rounds of 1024
 // keys in index order (four per thread, loaded together so that a round's loads are in
 // flight at once).  A key's rank among the equal digits of its wave comes from ballots
-// over the digit's bits; the first position of each (key of the thread, wave) group
-// per digit from a scan of the groups' counts in LDS.  The counts and the positions
-// have arrays of their own, so a round needs two barriers: the scan clears the counts
-// it has read, and the next round's counts are written after the barrier that
-// precedes this round's scatter.
+// over the digit's bits, the first position of each (key of the thread, wave) group per
+// digit from a scan of the groups' counts in LDS.  The round is first ordered by digit
+// in LDS and then written out by consecutive threads in that order, so that a store
+// covers a few contiguous runs of its digits' ranges instead of up to one per digit.
+// The counts have an array of their own that the scan clears after reading it.
 constexpr int kScatterPer = 4;
+constexpr int kScatterRound = kScatterPer * 256;
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
                                                        const uint32_t *recs_in, uint32_t *keys_out,
@@ -915,8 +916,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
                                                        int shift, const uint32_t *hist_off)
 {
     constexpr int kSub = kScatterPer * 4;   // groups of a round, in index order: (u, wave)
-    __shared__ uint32_t run[kRadixBuckets];
+    __shared__ uint32_t run[kRadixBuckets];       // the digit's next output position
+    __shared__ uint32_t gbase[kRadixBuckets];     // output position minus round slot, per digit
     __shared__ uint32_t cnt[kSub][kRadixBuckets], first[kSub][kRadixBuckets];
+    __shared__ uint32_t s_key[kScatterRound], s_val[kScatterRound], s_rec[kScatterRound];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid < kRadixBuckets) run[tid] = hist_off[(size_t)tid * kSortGrid + blockIdx.x];
     for (int e = tid; e < kSub * kRadixBuckets; e += 256) (&cnt[0][0])[e] = 0;
@@ -924,7 +927,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
     uint64_t lo, hi;
     sort_range(*nptr, lo, hi);
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint64_t base = lo; base < hi; base += kScatterPer * 256) {
+    for (uint64_t base = lo; base < hi; base += kScatterRound) {
         uint32_t key[kScatterPer], val[kScatterPer], rec[kScatterPer], d[kScatterPer], rank[kScatterPer];
         bool valid[kScatterPer];
 #pragma unroll
@@ -949,25 +952,56 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys_in, 
             if (valid[u] && rank[u] == 0) cnt[u * 4 + wave][d[u]] = (uint32_t)__builtin_popcountll(peers);
         }
         __syncthreads();
-        if (tid < kRadixBuckets) {
-            uint32_t pos = run[tid];
+        if (wave == 0) {
+            // lane dg < 32 scans digit dg's groups; the round's digit totals are then
+            // scanned across those lanes for the digit's first slot of the round
+            const int dg = lane & (kRadixBuckets - 1);
+            uint32_t tot = 0;
+            uint32_t c[kSub];
+#pragma unroll
             for (int g = 0; g < kSub; ++g) {
-                const uint32_t c = cnt[g][tid];
-                cnt[g][tid] = 0;
-                first[g][tid] = pos;
-                pos += c;
+                c[g] = cnt[g][dg];
+                tot += c[g];
             }
-            run[tid] = pos;
+            uint32_t x = lane < kRadixBuckets ? tot : 0u;   // inclusive scan over the digits
+            for (int o = 1; o < kRadixBuckets; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane < kRadixBuckets) {
+                uint32_t slot = x - tot;
+                gbase[dg] = run[dg] - slot;
+                run[dg] += tot;
+#pragma unroll
+                for (int g = 0; g < kSub; ++g) {
+                    cnt[g][dg] = 0;
+                    first[g][dg] = slot;
+                    slot += c[g];
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kScatterPer; ++u)
             if (valid[u]) {
-                const uint32_t pos = first[u * 4 + wave][d[u]] + rank[u];
-                keys_out[pos] = key[u];
-                vals_out[pos] = val[u];
-                recs_out[pos] = rec[u];
+                const uint32_t e = first[u * 4 + wave][d[u]] + rank[u];
+                s_key[e] = key[u];
+                s_val[e] = val[u];
+                s_rec[e] = rec[u];
             }
+        __syncthreads();
+        const uint64_t nr = hi - base < (uint64_t)kScatterRound ? hi - base : (uint64_t)kScatterRound;
+#pragma unroll
+        for (int u = 0; u < kScatterPer; ++u) {
+            const int e = u * 256 + tid;
+            if ((uint64_t)e < nr) {
+                const uint32_t k = s_key[e];
+                const uint32_t pos = gbase[(k >> shift) & (kRadixBuckets - 1u)] + (uint32_t)e;
+                keys_out[pos] = k;
+                vals_out[pos] = s_val[e];
+                recs_out[pos] = s_rec[e];
+            }
+        }
     }
 }
 
