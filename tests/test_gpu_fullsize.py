@@ -148,11 +148,11 @@ def test_config4_batched_active_sampled():
     run_case(sc, 24, 5, active_fraction=0.05, tile=32)
 
 
-@pytest.mark.parametrize("batch", [64, 128])
+@pytest.mark.parametrize("batch", [32, 64, 128, 256])
 def test_config4_timed_step_second_selection(batch):
     """The benchmark's steady-state forward: config 4 at tile 32 with the label changes
     of a second top-k selection (both signs) folded into pre in the same launch as the
-    active entries (App. A, BAN + BAU), at the LDS batches the tuner picks."""
+    active entries (App. A, BAN + BAU), at each LDS batch the tuner may pick."""
     sc = scenes.make_scene(4)
     log(f"config 4, 5% active, second selection, tile 32, batch {batch}")
     run_case(sc, 24, 7 + batch, active_fraction=0.05, tile=32, batch=batch, reselect=True)
