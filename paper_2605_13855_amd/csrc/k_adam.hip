@@ -26,6 +26,7 @@ struct AdamArgs {
 constexpr int kAdamThreads = 256;
 constexpr int kRows = 64;
 constexpr unsigned kAdamTiles = 1024;
+constexpr int kUnroll = 4;
 
 template <int C>
 __device__ void adam_group(const AdamArgs &a, int grp, int64_t na, float bc1, float bc2, float *s_g,
@@ -38,21 +39,47 @@ __device__ void adam_group(const AdamArgs &a, int grp, int64_t na, float bc1, fl
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * kRows;
         const int rows = (int)min((int64_t)kRows, na - r0);
-        for (int e = threadIdx.x; e < C * kRows; e += kAdamThreads) {
-            const int c = e / kRows, j = e % kRows;
-            if (j < rows) s_g[c * (kRows + 1) + j] = g[(size_t)c * a.gstride + r0 + j];
+        // the element loops take kUnroll elements per thread per pass, their loads issued
+        // before any is used, so that a pass waits on memory once
+#pragma unroll
+        for (int e0 = 0; e0 < C * kRows; e0 += kUnroll * kAdamThreads) {
+            float gv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int e = e0 + u * kAdamThreads + threadIdx.x, c = e / kRows, j = e % kRows;
+                gv[u] = e < C * kRows && j < rows ? g[(size_t)c * a.gstride + r0 + j] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int e = e0 + u * kAdamThreads + threadIdx.x, c = e / kRows, j = e % kRows;
+                if (e < C * kRows && j < rows) s_g[c * (kRows + 1) + j] = gv[u];
+            }
         }
         if (threadIdx.x < rows) s_id[threadIdx.x] = a.idx ? (int64_t)a.idx[r0 + threadIdx.x] : r0 + threadIdx.x;
         __syncthreads();
-        for (int e = threadIdx.x; e < rows * C; e += kAdamThreads) {
-            const int j = e / C, c = e % C;
-            const size_t pi = (size_t)s_id[j] * C + c;
-            const float gg = s_g[c * (kRows + 1) + j];
-            const float mm = a.b1 * m[pi] + (1.f - a.b1) * gg;
-            const float vv = a.b2 * v[pi] + (1.f - a.b2) * gg * gg;
-            m[pi] = mm;
-            v[pi] = vv;
-            p[pi] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + a.eps);
+        for (int e0 = 0; e0 < rows * C; e0 += kUnroll * kAdamThreads) {
+            size_t pi[kUnroll];
+            float gg[kUnroll], m0[kUnroll], v0[kUnroll], p0[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int e = e0 + u * kAdamThreads + threadIdx.x;
+                const bool ok = e < rows * C;
+                const int j = ok ? e / C : 0, c = ok ? e % C : 0;
+                pi[u] = (size_t)s_id[j] * C + c;
+                gg[u] = s_g[c * (kRows + 1) + j];
+                m0[u] = ok ? m[pi[u]] : 0.f;
+                v0[u] = ok ? v[pi[u]] : 0.f;
+                p0[u] = ok ? p[pi[u]] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (e0 + u * kAdamThreads + (int)threadIdx.x >= rows * C) continue;
+                const float mm = a.b1 * m0[u] + (1.f - a.b1) * gg[u];
+                const float vv = a.b2 * v0[u] + (1.f - a.b2) * gg[u] * gg[u];
+                m[pi[u]] = mm;
+                v[pi[u]] = vv;
+                p[pi[u]] = p0[u] - lr * (mm / bc1) / (sqrtf(vv / bc2) + a.eps);
+            }
         }
         __syncthreads();
     }
